@@ -1,0 +1,169 @@
+"""FP64 CPU oracle of the FSBM collision-coalescence step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_2409_07232_amd``) and the GPU library
+never imports it.
+
+The arithmetic lives in ``fsbm_oracle.c`` (plain loops, FP64, built with
+``-ffp-contract=off``); this module only builds it with gcc and marshals
+numpy arrays through ctypes.  ``closed_forms`` holds the analytic solutions
+of the collection equation used to pin the oracle.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fsbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+          "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("nbins", ctypes.c_int32),
+        ("nspecies", ctypes.c_int32),
+        ("nlevels", ctypes.c_int32),
+        ("s", ctypes.c_int32),
+        ("x1_g", ctypes.c_double),
+        ("theta", ctypes.c_double),
+        ("tables", ctypes.POINTER(ctypes.c_double)),
+        ("p_levels", ctypes.POINTER(ctypes.c_double)),
+        ("product", ctypes.POINTER(ctypes.c_int32)),
+        ("order", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        lib.fsbm_oracle_run.argtypes = [ctypes.POINTER(_Desc), dp, dp,
+                                        ctypes.c_int64, ctypes.c_double,
+                                        ctypes.c_int32, dp, dp, dp, dp, lp,
+                                        ctypes.c_int32]
+        lib.fsbm_oracle_run.restype = ctypes.c_int
+        lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
+        lib.fsbm_oracle_grid.restype = ctypes.c_int
+        lib.fsbm_oracle_targets.argtypes = [ctypes.POINTER(_Desc), ip, dp]
+        lib.fsbm_oracle_targets.restype = ctypes.c_int
+        lib.fsbm_oracle_flux_fraction.argtypes = [ctypes.c_double,
+                                                  ctypes.c_double]
+        lib.fsbm_oracle_flux_fraction.restype = ctypes.c_double
+        lib.fsbm_oracle_kernel_at.argtypes = [ctypes.POINTER(_Desc),
+                                              ctypes.c_double, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32]
+        lib.fsbm_oracle_kernel_at.restype = ctypes.c_double
+        lib.fsbm_oracle_max_threads.argtypes = []
+        lib.fsbm_oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class OracleModel:
+    """Create-time description of one bin grid and its species set."""
+
+    nbins: int
+    nspecies: int
+    tables: np.ndarray           # [S(S+1)/2][L][B][B] float64
+    p_levels: np.ndarray         # [L] float64, strictly decreasing
+    product: np.ndarray          # [S][S] int32
+    x1_g: float = 3.3510321638291124e-11
+    s: int = 1
+    theta: float = 1e-30
+
+    def __post_init__(self):
+        self.tables = np.ascontiguousarray(self.tables, dtype=np.float64)
+        self.p_levels = np.ascontiguousarray(self.p_levels, dtype=np.float64)
+        self.product = np.ascontiguousarray(self.product, dtype=np.int32)
+        self.nlevels = int(self.p_levels.shape[0])
+        self._desc = _Desc(
+            self.nbins, self.nspecies, self.nlevels, self.s, self.x1_g,
+            self.theta, _dptr(self.tables), _dptr(self.p_levels),
+            self.product.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0)
+
+    def grid(self) -> np.ndarray:
+        x = np.empty(self.nbins)
+        if _load().fsbm_oracle_grid(ctypes.byref(self._desc), _dptr(x)):
+            raise ValueError("bad oracle description")
+        return x
+
+    def targets(self):
+        k = np.empty((self.nbins, self.nbins), dtype=np.int32)
+        c = np.empty((self.nbins, self.nbins))
+        rc = _load().fsbm_oracle_targets(
+            ctypes.byref(self._desc),
+            k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(c))
+        if rc:
+            raise ValueError("bad oracle description")
+        return k, c
+
+    def kernel_at(self, p, a, b, i, j) -> float:
+        return _load().fsbm_oracle_kernel_at(ctypes.byref(self._desc),
+                                             float(p), a, b, i, j)
+
+    def run(self, N: np.ndarray, p: np.ndarray, dt: float, nsteps: int,
+            nthreads: int = 0, totals: bool = False):
+        """Advance ``N`` ([P][S][B] float64, modified in place)."""
+        if N.dtype != np.float64 or not N.flags.c_contiguous:
+            raise ValueError("N must be C-contiguous float64")
+        P = int(N.shape[0])
+        if N.size != P * self.nspecies * self.nbins:
+            raise ValueError("N has the wrong shape")
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        if p.shape[0] != P:
+            raise ValueError("p has the wrong length")
+        outs = [np.empty(P) for _ in range(4)] if totals else [None] * 4
+        lim = ctypes.c_int64(0)
+        rc = _load().fsbm_oracle_run(
+            ctypes.byref(self._desc), _dptr(N), _dptr(p), P, float(dt),
+            int(nsteps), *[(_dptr(o) if o is not None else None)
+                           for o in outs], ctypes.byref(lim), int(nthreads))
+        if rc:
+            raise ValueError("oracle rejected its input")
+        if totals:
+            return {"mass_before": outs[0], "mass_after": outs[1],
+                    "num_before": outs[2], "num_after": outs[3],
+                    "limiter_steps": int(lim.value)}
+        return {"limiter_steps": int(lim.value)}
+
+
+def flux_fraction(c: float, x1: float) -> float:
+    return _load().fsbm_oracle_flux_fraction(float(c), float(x1))
+
+
+def max_threads() -> int:
+    return int(_load().fsbm_oracle_max_threads())

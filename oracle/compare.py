@@ -1,0 +1,51 @@
+"""Error metrics between a candidate state and the oracle's state.
+
+TEST INFRASTRUCTURE ONLY (part of the oracle package).
+
+rel_bin: max over points, species and bins of
+    |M_cand - M_ref| / max(|M_ref|, 1e-9 * M_tot,ref)
+so bins holding less than 1e-9 of their point's mass are judged on an
+absolute scale.  drift: max over points of |sum M_end - sum M_0| / sum M_0.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def masses(N: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """[P][S][B] numbers -> masses."""
+    return N * x[None, None, :]
+
+
+def rel_bin(N_cand, N_ref, x, floor=1e-9):
+    Mc = masses(np.asarray(N_cand, dtype=np.float64), x)
+    Mr = masses(np.asarray(N_ref, dtype=np.float64), x)
+    P = Mr.shape[0]
+    tot = Mr.reshape(P, -1).sum(axis=1)
+    den = np.maximum(np.abs(Mr), floor * tot[:, None, None])
+    err = np.abs(Mc - Mr)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = np.where(den > 0, err / np.where(den > 0, den, 1.0),
+                     np.where(err > 0, np.inf, 0.0))
+    return float(r.max()) if r.size else 0.0
+
+
+def drift(N_end, N_start, x):
+    P = N_start.shape[0]
+    m0 = masses(N_start, x).reshape(P, -1).sum(axis=1)
+    m1 = masses(N_end, x).reshape(P, -1).sum(axis=1)
+    ok = m0 > 0
+    if not ok.any():
+        return 0.0
+    return float(np.max(np.abs(m1[ok] - m0[ok]) / m0[ok]))
+
+
+def l1_point(N_cand, N_ref, x):
+    Mc = masses(N_cand, x)
+    Mr = masses(N_ref, x)
+    P = Mr.shape[0]
+    tot = Mr.reshape(P, -1).sum(axis=1)
+    d = np.abs(Mc - Mr).reshape(P, -1).sum(axis=1)
+    ok = tot > 0
+    return float(np.max(d[ok] / tot[ok])) if ok.any() else 0.0

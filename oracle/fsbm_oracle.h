@@ -1,0 +1,79 @@
+/*
+ * fsbm_oracle.h -- plain FP64 CPU oracle of the FSBM collision-coalescence
+ * step (stochastic collection equation, Bott-style flux redistribution).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library.
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant with
+ * the GPU library and the GPU library never calls it.
+ *
+ * What it computes (per grid point, per time step; the paper names the
+ * routine as Bott's flux method for the collision term of the bin equation,
+ * Sec. III eq. (1), and describes per-point pressure-interpolated kernel
+ * tables, Sec. V-A "Lookup optimization"):
+ *   S1  M = N*x, M_tot (species then bins, ascending); M_tot == 0 -> unchanged
+ *   S2  bin active iff M >= theta*M_tot
+ *   S3  K(p) piecewise-linear between tabulated pressure levels, clamped
+ *   S4  canonical pair loop, Bott exponential-profile flux fraction
+ *   S5  positivity limiter (only when some bin is over-demanded)
+ *   S6  M' = M + (G - L), negative round-off clamped to 0, N' = M'/x
+ *   S7  per-point mass / number before and after the call
+ * Every arithmetic choice the paper leaves open is listed in the design doc.
+ *
+ * Units: N in cm^-3 per bin, x in g, K in cm^3 s^-1, p in hPa, dt in s.
+ */
+#ifndef FSBM_ORACLE_H
+#define FSBM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t nbins;            /* B >= 2 */
+  int32_t nspecies;         /* S in [1, 8] */
+  int32_t nlevels;          /* L >= 1 */
+  int32_t s;                /* bin mass ratio 2^(1/s), s >= 1 */
+  double x1_g;              /* mass of bin 0 in g */
+  double theta;             /* activity threshold relative to M_tot */
+  const double *tables;     /* [S(S+1)/2][L][B][B]; pair (a,b), a<=b, entry
+                               [i][j] = species a bin i with species b bin j */
+  const double *p_levels;   /* [L], hPa, strictly decreasing */
+  const int32_t *product;   /* [S*S] product species of (a,b), symmetric */
+  int32_t order;            /* 0 = simultaneous update (the only mode) */
+} fsbm_oracle_desc;
+
+/* Advance npoints independent points by nsteps steps of dt, in place.
+ * N: host [npoints][S][B].  p: host [npoints].  Optional outputs (may be
+ * NULL): per-point total mass / number before the first and after the last
+ * step, and the number of point-steps in which the limiter fired.
+ * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad input. */
+int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
+                    int64_t npoints, double dt, int32_t nsteps,
+                    double *mass_before, double *mass_after,
+                    double *num_before, double *num_after,
+                    int64_t *limiter_steps, int32_t nthreads);
+
+/* Bin masses x_k, k = 0..B-1. */
+int fsbm_oracle_grid(const fsbm_oracle_desc *d, double *x);
+
+/* Target bin k_ij and Courant number c_ij for every bin pair, [B][B].
+ * k = -1 marks a pair whose merged mass leaves the grid. */
+int fsbm_oracle_targets(const fsbm_oracle_desc *d, int32_t *k, double *c);
+
+/* Flux fraction f(c, x1) after the clamp to [0, 1]. */
+double fsbm_oracle_flux_fraction(double c, double x1);
+
+/* Interpolated kernel entry K^{ab}_{ij}(p). */
+double fsbm_oracle_kernel_at(const fsbm_oracle_desc *d, double p, int32_t a,
+                             int32_t b, int32_t i, int32_t j);
+
+/* Number of threads OpenMP would use. */
+int fsbm_oracle_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

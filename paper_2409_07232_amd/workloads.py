@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the collision step.
+
+This module only DECIDES INPUTS: bin grids used to lay out spectra and kernel
+tables, collection-kernel tables at pressure levels, initial spectra, cloudy
+masks and point pressures.  It holds none of the collision arithmetic and is
+shared by the GPU tests and the oracle tests alike.
+
+The paper benchmarks on the CONUS-12km WRF case (425 x 300 x 50 points,
+dt = 5 s; Sec. IV) whose data and FSBM kernel files are not available here.
+These generators stand in for them with the shapes of that workload: 33 mass
+doubling bins per particle type (Sec. III), kernel tables at several pressure
+levels interpolated per point (Sec. V-A), and a minority of cloudy points
+(Sec. VII discusses that many cells hold no cloud).
+
+Seeds: numpy PCG64(240907232 + config_id).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 240907232
+RHO_WATER = 1.0                                   # g cm^-3
+R1_CM = 2.0e-4                                    # 2 um smallest drop
+X1_G = 4.0 / 3.0 * np.pi * R1_CM ** 3 * RHO_WATER  # 3.351e-11 g
+P_LEVELS_3 = np.array([1000.0, 750.0, 500.0])
+
+# Config-3 species: liquid drops, ice crystals, snow, graupel.
+SPECIES_4 = ("liquid", "ice", "snow", "graupel")
+BETA_4 = (0.8, 0.3, 0.4, 0.6)
+RHO_4 = (1.0, 0.9, 0.1, 0.4)
+# product species of a collision, symmetric: l+l->l, i+i->s, s+s->s,
+# g+g->g, l+i->g, l+s->s, l+g->g, i+s->s, i+g->g, s+g->g
+PRODUCT_4 = np.array([[0, 3, 2, 3],
+                      [3, 2, 2, 3],
+                      [2, 2, 2, 3],
+                      [3, 3, 3, 3]], dtype=np.int32)
+# Config-4 species: liquid and graupel.
+PRODUCT_2 = np.array([[0, 1], [1, 1]], dtype=np.int32)
+
+
+@dataclass
+class Workload:
+    """One bin grid with its species set, tables and point states."""
+
+    name: str
+    nbins: int
+    nspecies: int
+    s: int
+    tables: np.ndarray            # [S(S+1)/2][L][B][B] float64, cm^3/s
+    p_levels: np.ndarray          # [L] hPa, strictly decreasing
+    product: np.ndarray           # [S][S] int32
+    N: np.ndarray                 # [P][S][B] float64, cm^-3 per bin
+    p: np.ndarray                 # [P] float64, hPa
+    dt: float
+    nsteps: int
+    x1_g: float = X1_G
+    theta: float = 1e-30
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def npoints(self) -> int:
+        return int(self.N.shape[0])
+
+    def cloudy(self) -> np.ndarray:
+        return np.any(self.N.reshape(self.npoints, -1) > 0.0, axis=1)
+
+    def subset(self, idx) -> "Workload":
+        """The same model on a subset of its points (copied)."""
+        idx = np.asarray(idx)
+        return Workload(self.name + "[subset]", self.nbins, self.nspecies,
+                        self.s, self.tables, self.p_levels, self.product,
+                        np.ascontiguousarray(self.N[idx]),
+                        np.ascontiguousarray(self.p[idx]), self.dt,
+                        self.nsteps, self.x1_g, self.theta, dict(self.meta))
+
+
+def rng_for(config_id: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + config_id))
+
+
+def bin_masses(nbins: int, s: int = 1, x1: float = X1_G) -> np.ndarray:
+    """x_k = x_1 2^(k/s), built with ldexp so that doubling is exact."""
+    k = np.arange(nbins)
+    return np.ldexp(x1 * np.power(2.0, (k % s) / s), k // s)
+
+
+def radius_cm(x_g, rho):
+    return np.cbrt(3.0 * np.asarray(x_g) / (4.0 * np.pi * rho))
+
+
+def golovin_tables(nbins, s=1, b=1500.0, x1=X1_G, nlevels=1):
+    """K_ij = b (x_i + x_j), identical at every level, one species."""
+    x = bin_masses(nbins, s, x1)
+    K = b * (x[:, None] + x[None, :])
+    return np.ascontiguousarray(np.broadcast_to(K, (1, nlevels, nbins,
+                                                    nbins)))
+
+
+def constant_tables(nbins, C, nlevels=1):
+    return np.full((1, nlevels, nbins, nbins), float(C))
+
+
+def gravitational_tables(nbins, s, rho, beta, vcoef, p_levels,
+                         x1=X1_G):
+    """Hydrodynamic kernel K = pi (r_a + r_b)^2 |v_a - v_b| (efficiency 1)
+    for every species pair a <= b, at each pressure level, with fall speeds
+    v = vcoef_a r^beta_a (cm/s, r in cm) scaled by (1000 / p)^0.4."""
+    S = len(rho)
+    x = bin_masses(nbins, s, x1)
+    r = [radius_cm(x, rho[a]) for a in range(S)]
+    npairs = S * (S + 1) // 2
+    L = len(p_levels)
+    out = np.empty((npairs, L, nbins, nbins))
+    q = 0
+    for a in range(S):
+        for b in range(a, S):
+            for li, pl in enumerate(p_levels):
+                scale = (1000.0 / pl) ** 0.4
+                va = vcoef[a] * r[a] ** beta[a] * scale
+                vb = vcoef[b] * r[b] ** beta[b] * scale
+                out[q, li] = (np.pi * (r[a][:, None] + r[b][None, :]) ** 2 *
+                              np.abs(va[:, None] - vb[None, :]))
+            q += 1
+    return out
+
+
+def liquid_tables(nbins, s=1, p_levels=P_LEVELS_3):
+    return gravitational_tables(nbins, s, (RHO_WATER,), (0.8,), (8.0e3,),
+                                p_levels)
+
+
+def multi_species_vcoef(beta):
+    # every species falls at the same speed at r = 100 um
+    return tuple(8.0e3 * 0.01 ** (0.8 - b) for b in beta)
+
+
+def gamma_spectrum_masses(x, rho, nu, rbar_cm, mtot):
+    """Bin masses of a gamma spectrum in radius, n(r) ~ r^nu e^{-(nu+1)r/rbar},
+    point-sampled on the mass grid (mass per bin ~ x r n(r)) and scaled to
+    the total mass mtot; rows are points."""
+    r = radius_cm(x, rho)[None, :]
+    nu = np.asarray(nu, dtype=np.float64)[:, None]
+    logm = np.log(x)[None, :] + (nu + 1.0) * np.log(r) - (nu + 1.0) * r / \
+        rbar_cm
+    logm -= logm.max(axis=1, keepdims=True)
+    m = np.exp(logm)
+    m *= (np.asarray(mtot, dtype=np.float64)[:, None] /
+          m.sum(axis=1, keepdims=True))
+    return m
+
+
+def _log_uniform(rng, lo, hi, n):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+
+
+# ---------------------------------------------------------------- config 1
+def config1(npoints: int = 64, nsteps: int = 1800, dt: float = 1.0,
+            s: int = 1, nbins: Optional[int] = None, b: float = 1500.0,
+            lwc_g_m3: float = 1.0, rbar_cm: float = 1.0e-3) -> Workload:
+    """Golovin kernel, one species, exponential start (identical points)."""
+    B = nbins if nbins is not None else 33 * s
+    x = bin_masses(B, s)
+    xbar = 4.0 / 3.0 * np.pi * rbar_cm ** 3 * RHO_WATER
+    L = lwc_g_m3 * 1e-6
+    N0 = L / xbar
+    n0 = N0 / xbar * np.exp(-x / xbar)
+    M = x * x * n0 * (np.log(2.0) / s)
+    M *= L / M.sum()
+    N = np.ascontiguousarray(np.broadcast_to(M / x, (npoints, 1, B)))
+    return Workload("golovin", B, 1, s, golovin_tables(B, s, b),
+                    np.array([1000.0]), np.zeros((1, 1), np.int32), N,
+                    np.full(npoints, 1000.0), dt, nsteps,
+                    meta={"b": b, "N0": N0, "xbar": xbar, "L": L})
+
+
+def constant_kernel(npoints=1, nsteps=1800, dt=1.0, s=1, C=1e-5,
+                    lwc_g_m3=1.0, rbar_cm=1.0e-3) -> Workload:
+    B = 33 * s
+    x = bin_masses(B, s)
+    xbar = 4.0 / 3.0 * np.pi * rbar_cm ** 3 * RHO_WATER
+    L = lwc_g_m3 * 1e-6
+    N0 = L / xbar
+    n0 = N0 / xbar * np.exp(-x / xbar)
+    M = x * x * n0 * (np.log(2.0) / s)
+    M *= L / M.sum()
+    N = np.ascontiguousarray(np.broadcast_to(M / x, (npoints, 1, B)))
+    return Workload("constant", B, 1, s, constant_tables(B, C),
+                    np.array([1000.0]), np.zeros((1, 1), np.int32), N,
+                    np.full(npoints, 1000.0), dt, nsteps,
+                    meta={"C": C, "N0": N0, "xbar": xbar, "L": L})
+
+
+# ---------------------------------------------------------------- config 2
+def config2(nx: int = 256, ny: int = 256, nz: int = 50, nsteps: int = 100,
+            dt: float = 2.0, cloudy_frac: float = 0.15) -> Workload:
+    """One GPU's patch of a thunderstorm domain, liquid only, 33 bins.
+    Point index = (level * ny + y) * nx + x; pressure falls linearly with
+    level from 1000 to 500 hPa."""
+    rng = rng_for(2)
+    B = 33
+    P = nx * ny * nz
+    x = bin_masses(B)
+    cloudy = rng.random(P) < cloudy_frac
+    idx = np.flatnonzero(cloudy)
+    nc = idx.size
+    nu = rng.uniform(2.0, 6.0, nc)
+    lwc = _log_uniform(rng, 0.1, 3.0, nc)
+    M = gamma_spectrum_masses(x, RHO_WATER, nu, 1.0e-3, lwc * 1e-6)
+    N = np.zeros((P, 1, B))
+    N[idx, 0, :] = M / x[None, :]
+    level = np.arange(P) // (nx * ny)
+    p = 1000.0 - 500.0 * level / max(nz - 1, 1)
+    return Workload("thunderstorm_patch", B, 1, 1, liquid_tables(B),
+                    P_LEVELS_3.copy(), np.zeros((1, 1), np.int32), N, p, dt,
+                    nsteps, meta={"shape": (nz, ny, nx),
+                                  "cloudy_frac": cloudy_frac})
+
+
+# ---------------------------------------------------------------- config 3
+def _multi_species_states(rng, x, rho, present, npoints, window):
+    """Per species: gamma spectrum with its own content; optional random
+    active window [lo, hi] outside which the spectrum is zeroed."""
+    S = len(rho)
+    B = x.size
+    N = np.zeros((npoints, S, B))
+    for a in range(S):
+        sel = np.flatnonzero(present[:, a])
+        n = sel.size
+        nu = rng.uniform(2.0, 6.0, n)
+        content = _log_uniform(rng, 0.1, 3.0, n)
+        M = gamma_spectrum_masses(x, rho[a], nu, 1.0e-3, content * 1e-6)
+        if window is not None:
+            lo = rng.integers(window[0][0], window[0][1] + 1, n)
+            hi = rng.integers(window[1][0], window[1][1] + 1, n)
+            kk = np.arange(B)[None, :]
+            M = np.where((kk >= lo[:, None]) & (kk <= hi[:, None]), M, 0.0)
+            # keep the species' content after windowing
+            tot = M.sum(axis=1, keepdims=True)
+            M *= (content[:, None] * 1e-6) / np.where(tot > 0, tot, 1.0)
+        N[sel, a, :] = M / x[None, :]
+    return N
+
+
+def config3(npoints: int = 1 << 20, nsteps: int = 100,
+            dt: float = 2.0) -> Workload:
+    """Four species with 10 interacting pair kernels, random ice presence and
+    uneven active-bin windows."""
+    rng = rng_for(3)
+    B, S = 33, 4
+    x = bin_masses(B)
+    present = np.ones((npoints, S), dtype=bool)
+    present[:, 1:] = rng.random((npoints, 3)) < 0.3
+    window = ((0, 5), (15, 32))
+    N = _multi_species_states(rng, x, RHO_4, present, npoints, window)
+    p = rng.uniform(500.0, 1000.0, npoints)
+    tables = gravitational_tables(B, 1, RHO_4, BETA_4,
+                                  multi_species_vcoef(BETA_4), P_LEVELS_3)
+    return Workload("four_species", B, S, 1, tables, P_LEVELS_3.copy(),
+                    PRODUCT_4.copy(), N, p, dt, nsteps,
+                    meta={"species": SPECIES_4})
+
+
+# ---------------------------------------------------------------- config 4
+def config4(nbins: int = 66, npoints: int = 262144, nsteps: int = 100,
+            dt: float = 2.0, config_id: int = 4) -> Workload:
+    """Liquid + graupel on a refined grid (66/132/264 bins, s = 2/4/8)."""
+    s = {66: 2, 132: 4, 264: 8}[nbins]
+    rng = rng_for(config_id)
+    rho = (RHO_4[0], RHO_4[3])
+    beta = (BETA_4[0], BETA_4[3])
+    x = bin_masses(nbins, s)
+    present = np.ones((npoints, 2), dtype=bool)
+    N = _multi_species_states(rng, x, rho, present, npoints, None)
+    p = rng.uniform(500.0, 1000.0, npoints)
+    tables = gravitational_tables(nbins, s, rho, beta,
+                                  multi_species_vcoef(beta), P_LEVELS_3)
+    return Workload("liquid_graupel_%d" % nbins, nbins, 2, s, tables,
+                    P_LEVELS_3.copy(), PRODUCT_2.copy(), N, p, dt, nsteps,
+                    meta={"species": ("liquid", "graupel")})
+
+
+# ---------------------------------------------------------------- config 5
+def config5(npoints: int = 1 << 22, nsteps: int = 100, dt: float = 2.0,
+            cloudy_frac: float = 0.10) -> List[Workload]:
+    """Mixed-grid batch: each point is assigned to the 33-bin four-species
+    grid (60%), the 66-bin or the 132-bin liquid+graupel grid (30%, 10%);
+    10% of points are cloudy.  Returns one workload per grid."""
+    rng = rng_for(5)
+    grid = rng.choice(3, size=npoints, p=[0.6, 0.3, 0.1])
+    cloudy = rng.random(npoints) < cloudy_frac
+    out = []
+    for g, (B, S, s) in enumerate(((33, 4, 1), (66, 2, 2), (132, 2, 4))):
+        sel = np.flatnonzero(grid == g)
+        n = sel.size
+        x = bin_masses(B, s)
+        cl = cloudy[sel]
+        if S == 4:
+            rho, beta, prod = RHO_4, BETA_4, PRODUCT_4
+            present = np.zeros((n, S), dtype=bool)
+            present[:, 0] = cl
+            present[:, 1:] = (rng.random((n, 3)) < 0.3) & cl[:, None]
+            window = ((0, 5), (15, 32))
+        else:
+            rho = (RHO_4[0], RHO_4[3])
+            beta = (BETA_4[0], BETA_4[3])
+            prod = PRODUCT_2
+            present = np.repeat(cl[:, None], 2, axis=1)
+            window = None
+        N = _multi_species_states(rng, x, rho, present, n, window)
+        p = rng.uniform(500.0, 1000.0, n)
+        tables = gravitational_tables(B, s, rho, beta,
+                                      multi_species_vcoef(beta), P_LEVELS_3)
+        out.append(Workload("mixed_%d" % B, B, S, s, tables,
+                            P_LEVELS_3.copy(), prod.copy(), N, p, dt, nsteps,
+                            meta={"global_index": sel}))
+    return out
+
+
+def sample_active(w: Workload, n: int, seed: int = 0) -> np.ndarray:
+    """Seeded subset of the cloudy point indices (sorted)."""
+    act = np.flatnonzero(w.cloudy())
+    if act.size <= n:
+        return act
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 1000 + seed))
+    return np.sort(rng.choice(act, size=n, replace=False))

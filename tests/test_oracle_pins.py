@@ -1,0 +1,454 @@
+"""Pins of the FP64 oracle against what the mathematics fixes.
+
+Each test checks the oracle against something other than itself: exact
+identities of the grid, quadrature of the flux-fraction integral, hand-worked
+one-step examples (tests/golden/), conservation laws, the Golovin and
+constant-kernel closed forms with their refinement ladders, exact
+invariances, and a 50-digit independent transcription on tiny inputs.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from oracle import closed_forms as cf
+from oracle import compare
+from paper_2409_07232_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LN1E60 = 60.0 * np.log(10.0)
+
+
+def model_of(w):
+    return oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
+                              w.product, x1_g=w.x1_g, s=w.s, theta=w.theta)
+
+
+def golovin_3bin(N0, N1, b=1500.0, x0=wl.X1_G):
+    tables = wl.golovin_tables(3, 1, b, x0)
+    om = oracle.OracleModel(3, 1, tables, np.array([1000.0]),
+                            np.zeros((1, 1), np.int32), x1_g=x0)
+    N = np.array([[[N0, N1, 0.0]]])
+    return om, N
+
+
+# ------------------------------------------------------------------ grid
+@pytest.mark.parametrize("s", [1, 2, 4, 8])
+def test_grid_ratio_exact(s):
+    w = wl.config1(npoints=1, s=s, nsteps=0)
+    x = model_of(w).grid()
+    assert x[0] == wl.X1_G
+    assert np.all(x[s:] == 2.0 * x[:-s])          # doubling is exact
+    ratio = x[1:] / x[:-1]
+    assert np.allclose(ratio, 2.0 ** (1.0 / s), rtol=1e-15)
+
+
+def test_targets_doubling_grid():
+    w = wl.config1(npoints=1, nsteps=0)
+    k, c = model_of(w).targets()
+    B = w.nbins
+    for i in range(B):
+        for j in range(B):
+            lo, hi = min(i, j), max(i, j)
+            if lo == hi:
+                want_k = hi + 1
+                want_c = 0.0
+            else:
+                want_k = hi
+                want_c = 2.0 ** (lo - hi)
+            if want_k >= B:
+                assert k[i, j] == -1
+                continue
+            assert k[i, j] == want_k
+            if want_k <= B - 2:
+                # c = ((x_i + x_j) - x_k) / (x_{k+1} - x_k): the rounding of
+                # the merged mass bounds its error absolutely, by ~2 ulp(1)
+                assert abs(c[i, j] - want_c) <= 4.5e-16
+
+
+@pytest.mark.parametrize("s", [2, 4])
+def test_targets_bracket_the_merged_mass(s):
+    w = wl.config1(npoints=1, s=s, nsteps=0)
+    om = model_of(w)
+    x = om.grid()
+    k, c = om.targets()
+    B = w.nbins
+    xe = wl.bin_masses(B + 2 * s + 2, s)
+    for i in range(B):
+        for j in range(B):
+            sm = x[i] + x[j]
+            if k[i, j] < 0:
+                assert sm * (1 + 1e-12) >= xe[B]
+                continue
+            kk = k[i, j]
+            assert x[kk] <= sm * (1 + 1e-12) < xe[kk + 1]
+            if kk <= B - 2:
+                assert 0.0 <= c[i, j] <= 1.0
+                assert x[kk] + c[i, j] * (x[kk + 1] - x[kk]) == \
+                    pytest.approx(sm, rel=1e-13)
+
+
+# ------------------------------------------------------------ flux fraction
+@pytest.mark.parametrize("c", [0.5, 0.25, 1.0 / 1024, 0.7, 0.999, 2.0 ** -30])
+@pytest.mark.parametrize("x1", [-138.0, -20.0, -1.0, -1e-3, 1e-6, 0.7, 3.0,
+                                12.0])
+def test_flux_fraction_is_the_profile_integral(c, x1):
+    q, _ = integrate.quad(lambda t: np.exp(x1 * t), 0.5 - c, 0.5,
+                          epsabs=0, epsrel=1e-13, limit=200)
+    want = min(max(q, 0.0), 1.0)
+    assert oracle.flux_fraction(c, x1) == pytest.approx(want, rel=1e-12,
+                                                        abs=1e-300)
+
+
+def test_flux_fraction_limits():
+    for c in (0.5, 0.125, 0.9):
+        assert oracle.flux_fraction(c, 0.0) == c
+        assert oracle.flux_fraction(c, 1e-12) == pytest.approx(c, rel=1e-11)
+        assert oracle.flux_fraction(c, 800.0) == 1.0
+    assert oracle.flux_fraction(0.0, -5.0) == 0.0
+    # monotone in x1 for c <= 1
+    xs = np.linspace(-138, 30, 400)
+    f = [oracle.flux_fraction(0.3, v) for v in xs]
+    assert np.all(np.diff(f) >= 0)
+
+
+# ------------------------------------------------------ worked examples
+def test_three_bin_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "three_bin_worked_example.json")))
+    b, x0, N0, N1, dt = (g["b_cm3_g_s"], g["x0_g"], g["N0_cm3"], g["N1_cm3"],
+                         g["dt_s"])
+    f = oracle.flux_fraction(0.5, -LN1E60)
+    assert abs(f - g["f_empty_neighbour_c_half"]) < g["f_tolerance_abs"]
+    om, N = golovin_3bin(N0, N1, b, x0)
+    x = om.grid()
+    assert x[1] == 2 * x0 and x[2] == 4 * x0
+    M0, M1 = N0 * x0, N1 * 2 * x0
+    K00, K01, K11 = b * 2 * x0, b * 3 * x0, b * 4 * x0
+    C00 = dt * K00 * N0 * N0 / 2
+    C01 = dt * K01 * N0 * N1
+    C11 = dt * K11 * N1 * N1 / 2
+    F01 = f * 3 * C01 * x0
+    want = np.array([M0 - 2 * C00 * x0 - C01 * x0,
+                     M1 + 2 * C00 * x0 + C01 * x0 - F01 - 4 * C11 * x0,
+                     F01 + 4 * C11 * x0])
+    res = om.run(N, np.array([1000.0]), dt, 1)
+    assert res["limiter_steps"] == 0
+    got = N[0, 0] * x
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+
+
+def test_forced_limiter_example():
+    g = json.load(open(os.path.join(GOLDEN, "forced_limiter_example.json")))
+    b, x0, N0, N1, dt = (g["b_cm3_g_s"], g["x0_g"], g["N0_cm3"], g["N1_cm3"],
+                         g["dt_s"])
+    om, N = golovin_3bin(N0, N1, b, x0)
+    x = om.grid()
+    f = oracle.flux_fraction(0.5, -LN1E60)
+    M0, M1 = N0 * x0, N1 * 2 * x0
+    C00 = dt * b * 2 * x0 * N0 * N0 / 2
+    C01 = dt * b * 3 * x0 * N0 * N1
+    C11 = dt * b * 4 * x0 * N1 * N1 / 2
+    F01 = f * 3 * C01 * x0
+    D0 = 2 * C00 * x0 + C01 * x0
+    D1 = 4 * C11 * x0
+    s0, s1 = M0 / D0, M1 / D1
+    assert s0 < 1 and s1 < 1
+    want = np.array([0.0,
+                     M1 + s0 * (2 * C00 * x0 + C01 * x0 - F01) -
+                     s1 * 4 * C11 * x0,
+                     s0 * F01 + s1 * 4 * C11 * x0])
+    res = om.run(N, np.array([1000.0]), dt, 1)
+    assert res["limiter_steps"] == 1
+    got = N[0, 0] * x
+    mt = M0 + M1
+    assert np.all(got >= 0)
+    assert np.allclose(got, want, rtol=0, atol=1e-14 * mt)
+
+
+def test_two_species_table_orientation():
+    """Species 0 bin i0 meets species 1 bin j0; the cross table is
+    deliberately asymmetric, so the loss of each bin in one step pins which
+    entry is read: K^{01}[i0][j0] (species 0 bin i0 with species 1 bin j0)."""
+    B = 6
+    x = wl.bin_masses(B)
+    t = np.zeros((3, 1, B, B))
+    rng = np.random.default_rng(7)
+    t[1, 0] = rng.uniform(1e-6, 1e-3, (B, B))   # cross kernel, asymmetric
+    i0, j0 = 1, 3
+    om = oracle.OracleModel(B, 2, t, np.array([1000.0]),
+                            np.array([[0, 1], [1, 1]], np.int32))
+    N = np.zeros((1, 2, B))
+    N[0, 0, i0] = 30.0
+    N[0, 1, j0] = 2.0
+    dt = 1.0
+    before = N.copy()
+    om.run(N, np.array([900.0]), dt, 1)
+    C = dt * t[1, 0, i0, j0] * 30.0 * 2.0
+    assert t[1, 0, i0, j0] != t[1, 0, j0, i0]
+    lost0 = (before[0, 0, i0] - N[0, 0, i0]) * x[i0]
+    assert lost0 == pytest.approx(C * x[i0], rel=1e-12)
+    # the merged mass goes to species P(0,1) = 1: bin 3 (x1+x3 = 10 x0)
+    gained = (N[0, 1] - before[0, 1]) * x
+    assert gained.sum() == pytest.approx(C * x[i0], rel=1e-10)
+
+
+# ---------------------------------------------------- pressure interpolation
+def test_pressure_interpolation_is_piecewise_linear():
+    B = 5
+    rng = np.random.default_rng(3)
+    alpha = rng.uniform(1e-4, 1e-3, (B, B))
+    beta = rng.uniform(1e-7, 1e-6, (B, B))
+    lev = np.array([1000.0, 750.0, 500.0])
+    t = (alpha[None] + beta[None] * lev[:, None, None])[None]
+    om = oracle.OracleModel(B, 1, t, lev, np.zeros((1, 1), np.int32))
+    for p in (999.0, 1000.0, 812.5, 750.0, 600.0, 500.0):
+        for (i, j) in ((0, 0), (1, 4), (3, 2)):
+            assert om.kernel_at(p, 0, 0, i, j) == pytest.approx(
+                alpha[i, j] + beta[i, j] * p, rel=1e-14)
+    # clamped outside the tabulated range, no extrapolation
+    assert om.kernel_at(1100.0, 0, 0, 1, 2) == pytest.approx(
+        alpha[1, 2] + beta[1, 2] * 1000.0, rel=1e-14)
+    assert om.kernel_at(200.0, 0, 0, 1, 2) == pytest.approx(
+        alpha[1, 2] + beta[1, 2] * 500.0, rel=1e-14)
+    # at an interior level the value is the tabulated one exactly
+    assert om.kernel_at(750.0, 0, 0, 1, 2) == t[0, 1, 1, 2]
+
+
+def test_step_uses_the_interpolated_kernel():
+    """A run on tables linear in p equals a run on one table K(p)."""
+    B = 8
+    x = wl.bin_masses(B)
+    lev = np.array([1000.0, 750.0, 500.0])
+    Kg = wl.golovin_tables(B)[0, 0]
+    t3 = np.stack([Kg * (1.0 + 0.4 * (1000.0 - pl) / 500.0) for pl in lev])
+    p = 640.0
+    t1 = (Kg * (1.0 + 0.4 * (1000.0 - p) / 500.0))[None, None]
+    N = np.zeros((1, 1, B))
+    N[0, 0, :5] = [200.0, 120.0, 50.0, 10.0, 1.0]
+    Na, Nb = N.copy(), N.copy()
+    oracle.OracleModel(B, 1, t3[None], lev, np.zeros((1, 1), np.int32)).run(
+        Na, np.array([p]), 5.0, 3)
+    oracle.OracleModel(B, 1, t1, np.array([1000.0]),
+                       np.zeros((1, 1), np.int32)).run(Nb, np.array([p]),
+                                                       5.0, 3)
+    assert compare.rel_bin(Na, Nb, x) < 1e-13
+
+
+# --------------------------------------------------- conservation laws
+def _check_laws(w, npts, nsteps):
+    om = model_of(w)
+    x = om.grid()
+    idx = wl.sample_active(w, npts)
+    sub = w.subset(idx)
+    N = sub.N.copy()
+    Ntot_prev = N.sum(axis=(1, 2))
+    for _ in range(nsteps):
+        om.run(N, sub.p, w.dt, 1)
+        assert np.all(N >= 0.0)                              # positivity
+        Ntot = N.sum(axis=(1, 2))
+        assert np.all(Ntot <= Ntot_prev * (1 + 1e-14))        # number
+        Ntot_prev = Ntot
+    d = compare.drift(N, sub.N, x)
+    assert d <= 1e-13                                        # mass
+    return d
+
+
+def test_laws_golovin_full_run():
+    w = wl.config1(npoints=1)
+    om = model_of(w)
+    x = om.grid()
+    N = w.N.copy()
+    r = om.run(N, w.p, w.dt, w.nsteps, totals=True)
+    assert r["limiter_steps"] == 0
+    assert np.all(N >= 0)
+    assert compare.drift(N, w.N, x) <= 1e-13
+    assert r["num_after"][0] < r["num_before"][0]
+
+
+def test_laws_thunderstorm_subset():
+    _check_laws(wl.config2(nx=16, ny=16, nz=50), 24, 40)
+
+
+def test_laws_four_species_subset():
+    _check_laws(wl.config3(npoints=512), 8, 20)
+
+
+def test_laws_refined_two_species_subset():
+    _check_laws(wl.config4(nbins=66, npoints=64), 3, 10)
+
+
+def test_laws_under_forced_limiter():
+    w = wl.config2(nx=8, ny=8, nz=50)
+    om = model_of(w)
+    x = om.grid()
+    sub = w.subset(wl.sample_active(w, 16))
+    N = sub.N.copy()
+    r = om.run(N, sub.p, 4000.0, 3, totals=True)
+    assert r["limiter_steps"] > 0
+    assert np.all(N >= 0)
+    assert compare.drift(N, sub.N, x) <= 1e-13
+    assert np.all(r["num_after"] <= r["num_before"] * (1 + 1e-13))
+
+
+# ------------------------------------------------------ closed forms
+def _golovin_errors(s, dt=1.0, t_end=1800.0):
+    w = wl.config1(npoints=1, s=s, dt=dt, nsteps=int(round(t_end / dt)))
+    om = model_of(w)
+    x = om.grid()
+    N = w.N.copy()
+    om.run(N, w.p, w.dt, w.nsteps)
+    m = w.meta
+    M = N[0, 0] * x
+    Mex = cf.bin_masses(lambda xx: cf.golovin_n(xx, t_end, m["N0"],
+                                                m["xbar"], m["b"]), x, s)
+    l1 = np.abs(M - Mex).sum() / m["L"]
+    num = N.sum() / cf.golovin_number(t_end, m["N0"], m["xbar"], m["b"])
+    m2 = (M * x).sum() / cf.golovin_m2(t_end, m["N0"], m["xbar"], m["b"])
+    return l1, num, m2, int(np.argmax(M)), int(np.argmax(Mex))
+
+
+def test_golovin_refinement_ladder():
+    res = {s: _golovin_errors(s) for s in (1, 2, 4)}
+    l1 = [res[s][0] for s in (1, 2, 4)]
+    assert l1[0] / l1[1] >= 2.5 and l1[1] / l1[2] >= 2.5
+    assert abs(res[1][1] - 1) < 0.16
+    assert abs(res[2][1] - 1) < 0.05
+    assert abs(res[4][1] - 1) < 0.015
+    assert abs(res[1][3] - res[1][4]) <= 2
+    # second moment M2 = M2(0) exp(2 b L t): error shrinks with refinement
+    m2err = [abs(res[s][2] - 1) for s in (1, 2, 4)]
+    assert m2err[0] > m2err[1] > m2err[2]
+
+
+def test_constant_kernel_refinement_ladder():
+    out = []
+    for s in (1, 2, 4):
+        w = wl.constant_kernel(npoints=1, s=s)
+        om = model_of(w)
+        x = om.grid()
+        N = w.N.copy()
+        om.run(N, w.p, w.dt, w.nsteps)
+        m = w.meta
+        t = w.nsteps * w.dt
+        M = N[0, 0] * x
+        Mex = cf.bin_masses(lambda xx: cf.constant_n(xx, t, m["N0"],
+                                                     m["xbar"], m["C"]), x, s)
+        l1 = np.abs(M - Mex).sum() / m["L"]
+        num = N.sum() / cf.constant_number(t, m["N0"], m["C"])
+        out.append((l1, num))
+    assert out[0][0] / out[1][0] >= 2.5 and out[1][0] / out[2][0] >= 2.5
+    assert abs(out[0][1] - 1) < 0.16
+    assert abs(out[1][1] - 1) < 0.05
+    assert abs(out[2][1] - 1) < 0.015
+
+
+def test_golovin_time_step_convergence():
+    l1 = [_golovin_errors(1, dt=dt, t_end=1800.0)[0] for dt in (1.0, 5.0,
+                                                                 10.0)]
+    assert l1[0] < l1[1] < l1[2]
+
+
+# ------------------------------------------------------ exact invariances
+def test_invariances():
+    w = wl.config2(nx=8, ny=8, nz=50)
+    om = model_of(w)
+    N = w.N.copy()
+    dry = ~w.cloudy()
+    assert dry.any()
+    om.run(N, w.p, w.dt, 5)
+    assert np.array_equal(N[dry], w.N[dry])       # no mass -> untouched
+    N0 = w.N.copy()
+    om.run(N0, w.p, w.dt, 0)
+    assert np.array_equal(N0, w.N)                # zero steps -> identity
+
+
+def test_pressure_independent_tables_give_p_independent_results():
+    w = wl.config1(npoints=4, nsteps=30)
+    t3 = np.repeat(w.tables, 3, axis=1)
+    om = oracle.OracleModel(w.nbins, 1, t3, wl.P_LEVELS_3.copy(), w.product)
+    Na = w.N.copy()
+    om.run(Na, np.array([1000.0, 900.0, 612.0, 500.0]), w.dt, w.nsteps)
+    assert np.array_equal(Na[0], Na[1]) and np.array_equal(Na[0], Na[3])
+
+
+def test_sub_threshold_bin_is_inert():
+    """A bin below theta * M_tot takes part in no pair: the other bins end
+    bitwise equal whether or not it holds a tiny seed."""
+    w = wl.config1(npoints=1, nsteps=20)
+    om = model_of(w)
+    N = w.N.copy()
+    N[0, 0, 30] = 0.0
+    Ns = N.copy()
+    x = om.grid()
+    Ns[0, 0, 30] = 1e-45 * (N[0, 0] * x).sum() / x[30]
+    om.run(N, w.p, w.dt, w.nsteps)
+    om.run(Ns, w.p, w.dt, w.nsteps)
+    keep = np.arange(w.nbins) != 30
+    assert np.array_equal(N[0, 0, keep], Ns[0, 0, keep])
+
+
+def test_species_relabelling():
+    w = wl.config4(nbins=66, npoints=16, nsteps=5)
+    om = model_of(w)
+    x = om.grid()
+    sub = w.subset(np.arange(4))
+    Na = sub.N.copy()
+    om.run(Na, sub.p, w.dt, w.nsteps)
+    t = w.tables
+    tp = np.stack([t[2], np.transpose(t[1], (0, 2, 1)), t[0]])
+    # species swapped: P'(a, b) = swap(P(swap(a), swap(b)))
+    prod = (1 - w.product[::-1, ::-1]).astype(np.int32)
+    om2 = oracle.OracleModel(w.nbins, 2, tp, w.p_levels, prod, s=w.s)
+    Nb = sub.N[:, ::-1, :].copy()
+    om2.run(Nb, sub.p, w.dt, w.nsteps)
+    assert compare.rel_bin(Nb[:, ::-1, :], Na, x) < 1e-13
+
+
+def test_determinism_and_thread_count_independence():
+    w = wl.config3(npoints=64)
+    om = model_of(w)
+    Na, Nb = w.N.copy(), w.N.copy()
+    om.run(Na, w.p, w.dt, 3, nthreads=1)
+    om.run(Nb, w.p, w.dt, 3, nthreads=4)
+    assert np.array_equal(Na, Nb)
+
+
+# ------------------------------------------ 50-digit tiny-case cross-check
+@pytest.mark.parametrize("seed", range(6))
+def test_tiny_cases_against_50_digit_transcription(seed):
+    import mpmath as mp
+
+    from tests import mp_reference as mr
+    rng = np.random.default_rng(100 + seed)
+    S = 1 + seed % 2
+    B = 4 + seed % 3
+    s = 1 + (seed // 3)
+    npair = S * (S + 1) // 2
+    lev = np.array([1000.0, 700.0])
+    tables = rng.uniform(1e-5, 5e-3, (npair, 2, B, B))
+    for q in range(npair):       # same-species tables are symmetric
+        a = [a for a in range(S) for b in range(a, S)][q]
+        b = [b for a in range(S) for b in range(a, S)][q]
+        if a == b:
+            tables[q] = 0.5 * (tables[q] + np.transpose(tables[q], (0, 2, 1)))
+    prod = np.zeros((S, S), np.int32)
+    if S == 2:
+        prod[:] = [[0, 1], [1, 1]]
+    N = rng.uniform(0.0, 50.0, (1, S, B))
+    N[0, :, rng.integers(0, B)] = 0.0           # an empty bin
+    p = float(rng.uniform(650, 1050))
+    dt, nsteps = 2.0, 3
+    om = oracle.OracleModel(B, S, tables, lev, prod, s=s)
+    x = om.grid()
+    Nc = N.copy()
+    om.run(Nc, np.array([p]), dt, nsteps)
+    Nm = [[mp.mpf(float(v)) for v in N[0, a]] for a in range(S)]
+    for _ in range(nsteps):
+        Nm = mr.step(Nm, p, dt, B, S, s, wl.X1_G, tables.tolist(),
+                     lev.tolist(), prod.tolist())
+    Nref = np.array([[[float(v) for v in Nm[a]] for a in range(S)]])
+    assert compare.rel_bin(Nc, Nref, x) < 1e-13
