@@ -1,0 +1,171 @@
+/*
+ * fsbm_coal.h -- C ABI of the MI355X (gfx950) collision-coalescence library.
+ *
+ * The library advances the bin spectra of many independent grid points by
+ * the collision-coalescence term of the bin equation (Sec. III, eq. (1)),
+ * solved with Bott's flux method (the routine the paper offloads, Sec. III
+ * and Sec. V), with the collection kernels of every pair of particle types
+ * tabulated at a few pressure levels and interpolated linearly for each
+ * point's pressure (Sec. V-A, "Lookup optimization"), and with the work
+ * restricted to cloudy points (the predicate array of Sec. V-B).
+ *
+ * All functions return 0 on success or a negative FSBM_E* code; none aborts
+ * or throws.  fsbm_coal_strerror() turns a code into text; the handle keeps
+ * the message of the last HIP error it saw.
+ *
+ * Units: N in cm^-3 per bin, bin masses in g, kernels in cm^3 s^-1, pressure
+ * in hPa, time in s.
+ */
+#ifndef FSBM_COAL_H
+#define FSBM_COAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define FSBM_OK 0
+#define FSBM_EINVAL (-1)       /* bad size, pointer, level order, dt, ... */
+#define FSBM_ENOMEM (-2)       /* device or host allocation failed */
+#define FSBM_EHIP (-3)         /* HIP runtime error (text kept in handle) */
+#define FSBM_EUNSUPPORTED (-4) /* valid but beyond what was compiled */
+#define FSBM_EDOMAIN (-5)      /* debug checks: negative or NaN input */
+
+/* arithmetic of the pair loop */
+#define FSBM_FP64 0  /* every step in FP64 */
+#define FSBM_FP32C 1 /* FP32 pair arithmetic with compensated per-bin sums,
+                        FP64 totals and FP64 final update */
+
+/* option flags */
+#define FSBM_FLAG_DEBUG_CHECKS 1 /* validate N (>= 0, finite) before a step */
+#define FSBM_FLAG_NO_GRAPH 2     /* launch kernels directly, no hipGraph */
+#define FSBM_FLAG_FORCE_WAVE 4   /* use the one-point-per-wave kernel even
+                                    where the one-point-per-lane one fits */
+#define FSBM_FLAG_PROFILE 8      /* launch directly (no hipGraph) and time
+                                    every collision-kernel launch with HIP
+                                    events on the caller's stream; see
+                                    fsbm_coal_stats.kernel_ms */
+
+typedef struct fsbm_coal_s *fsbm_coal_t;
+
+typedef struct {
+  double x1_g;              /* mass of bin 0; default 3.3510321638291124e-11
+                               (a 2 um water drop) */
+  int32_t s;                /* bin mass ratio 2^(1/s); default 1 (doubling) */
+  const int32_t *product;   /* [S*S] host, product species of a collision of
+                               species a and b, symmetric; NULL = default
+                               (every collision yields species 0 if S == 1;
+                               for S > 1 NULL is an error) */
+  int32_t precision;        /* FSBM_FP64 (default) or FSBM_FP32C */
+  double theta;             /* bin activity threshold relative to the point's
+                               total mass; default 1e-30 */
+  int32_t steps_per_launch; /* time steps fused into one kernel launch;
+                               0 = choose (tuning cache or default) */
+  int32_t flags;            /* FSBM_FLAG_* */
+} fsbm_coal_opts;
+
+/* Fill opts with the defaults above. */
+void fsbm_coal_opts_default(fsbm_coal_opts *opts);
+
+/*
+ * Create a handle for one bin grid and species set (Sec. V-A: collection
+ * kernels per particle-type pair at pressure levels).
+ *  nbins          B >= 2 bins per species (mass grid x_k = x1 2^(k/s))
+ *  nspecies       S in [1, 8]
+ *  kernel_tables  host, FP64, [S(S+1)/2][L][B][B]; species pairs in the order
+ *                 (0,0),(0,1),..,(0,S-1),(1,1),..; for pair (a,b) entry
+ *                 [l][i][j] is the kernel of species a bin i with species b
+ *                 bin j at level l.  Copied; the caller keeps ownership.
+ *  nlevels        L >= 1
+ *  p_levels_hpa   host, [L], strictly decreasing (e.g. 1000, 750, 500)
+ *  opts           NULL for defaults
+ *  out            receives the handle
+ * Errors: FSBM_EINVAL (sizes, levels, product map, non-finite or negative
+ * table entries), FSBM_ENOMEM, FSBM_EHIP.  Uses the current HIP device.
+ */
+int fsbm_coal_create(int32_t nbins, int32_t nspecies,
+                     const double *kernel_tables, int32_t nlevels,
+                     const double *p_levels_hpa, const fsbm_coal_opts *opts,
+                     fsbm_coal_t *out);
+
+/*
+ * Advance npoints grid points by nsteps collision steps of dt_s seconds
+ * (Sec. V-B: the offloaded collision loop over all points whose predicate
+ * holds; here a point takes part iff it holds mass).
+ *  N       device, FP64, C-contiguous [npoints][S][B], updated in place
+ *  p_hpa   device, FP64, [npoints] pressure of each point
+ *  stream  a hipStream_t (NULL = the default stream)
+ * Stream-ordered and asynchronous: returns once the work is enqueued.  Launch
+ * and argument errors are returned; device faults surface at the caller's
+ * next synchronisation.  npoints == 0 or nsteps == 0 is a no-op.  The caller
+ * owns N and p and keeps them alive until the stream has passed the step.
+ * One step may be in flight per handle (the handle owns the workspace).
+ */
+int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
+                   int64_t npoints, double dt_s, int32_t nsteps,
+                   void *stream);
+
+/*
+ * One launch sequence over several handles with different grids (mixed
+ * 33/66/132-bin batches): the cloudy points of every grid are compacted into
+ * one work list and advanced by one persistent kernel per group of fused
+ * steps.  Arrays are indexed by grid; same ownership rules as
+ * fsbm_coal_step.  All handles must use the same precision.
+ */
+int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
+                         double *const *N, const double *const *p_hpa,
+                         const int64_t *npoints, double dt_s, int32_t nsteps,
+                         void *stream);
+
+/*
+ * Explicitly autotune the launch shape (steps per launch, waves per block)
+ * for about npoints_hint cloudy points, timing candidates on synthetic
+ * states; every candidate is checked against the default shape first.
+ * Synchronises the stream.  The choice is kept in the handle and in the
+ * cache file named by the FSBM_TUNE_CACHE environment variable, if set.
+ */
+int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream);
+
+/*
+ * Per-point FP64 bookkeeping of the last fsbm_coal_step on this handle:
+ * total mass (g cm^-3) and number (cm^-3) of each point before the first and
+ * after the last step.  Each pointer is device [npoints] or NULL.  Enqueued
+ * on the stream of that step.
+ */
+int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
+                     double *num_before, double *num_after);
+
+typedef struct {
+  int64_t active_points;  /* cloudy points in the last step call */
+  int64_t pair_evals;     /* bin pairs evaluated (both bins active, merged
+                             mass inside the grid), summed over points and
+                             steps of the last call */
+  int64_t limiter_steps;  /* point-steps where the positivity limiter ran */
+  int64_t fp64_fallback_steps; /* FP32C point-steps redone in FP64 */
+  int32_t kernel;         /* 0 = one point per lane, 1 = one point per wave */
+  int32_t steps_per_launch;
+  int32_t waves_per_block;
+  int32_t kernel_launches; /* FSBM_FLAG_PROFILE: collision-kernel launches
+                              timed since the handle was created */
+  double kernel_ms;        /* FSBM_FLAG_PROFILE: their summed duration */
+} fsbm_coal_stats;
+
+/* Counters of the last step call.  Synchronises that call's stream. */
+int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out);
+
+/* Free every resource of the handle; NULL is accepted.  Using a handle after
+   destroy is undefined. */
+int fsbm_coal_destroy(fsbm_coal_t h);
+
+/* Static text for an error code. */
+const char *fsbm_coal_strerror(int code);
+
+/* Message of the last HIP error seen by the handle ("" if none). */
+const char *fsbm_coal_last_error(fsbm_coal_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,266 @@
+"""ctypes binding of the C ABI in ``include/fsbm_coal.h``.
+
+Argument marshalling only: every step of the collision path runs in the HIP
+library ``libfsbm_coal.so``.  Device memory and streams come from PyTorch
+(``torch.Tensor.data_ptr()``, ``torch.cuda.Stream.cuda_stream``).  There is no
+CPU fallback: if the library is missing, loading fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsbm_coal.so")
+
+FSBM_OK = 0
+FSBM_EINVAL = -1
+FSBM_ENOMEM = -2
+FSBM_EHIP = -3
+FSBM_EUNSUPPORTED = -4
+FSBM_EDOMAIN = -5
+FSBM_FP64 = 0
+FSBM_FP32C = 1
+FLAG_DEBUG_CHECKS = 1
+FLAG_NO_GRAPH = 2
+FLAG_FORCE_WAVE = 4
+FLAG_PROFILE = 8
+
+# every entry point declared in include/fsbm_coal.h
+EXPORTS = ("fsbm_coal_opts_default", "fsbm_coal_create", "fsbm_coal_step",
+           "fsbm_coal_step_multi", "fsbm_coal_tune", "fsbm_coal_totals",
+           "fsbm_coal_get_stats", "fsbm_coal_destroy", "fsbm_coal_strerror",
+           "fsbm_coal_last_error")
+
+
+class FsbmError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        msg = "%s failed: %s (%d)" % (where, strerror(code), code)
+        if detail:
+            msg += ": " + detail
+        super().__init__(msg)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("x1_g", ctypes.c_double),
+                ("s", ctypes.c_int32),
+                ("product", ctypes.POINTER(ctypes.c_int32)),
+                ("precision", ctypes.c_int32),
+                ("theta", ctypes.c_double),
+                ("steps_per_launch", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("active_points", ctypes.c_int64),
+                ("pair_evals", ctypes.c_int64),
+                ("limiter_steps", ctypes.c_int64),
+                ("fp64_fallback_steps", ctypes.c_int64),
+                ("kernel", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32),
+                ("kernel_launches", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            "libfsbm_coal.so is missing; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.fsbm_coal_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    lib.fsbm_coal_opts_default.restype = None
+    lib.fsbm_coal_create.argtypes = [ctypes.c_int32, ctypes.c_int32, dp,
+                                     ctypes.c_int32, dp,
+                                     ctypes.POINTER(Opts),
+                                     ctypes.POINTER(vp)]
+    lib.fsbm_coal_create.restype = ctypes.c_int
+    lib.fsbm_coal_step.argtypes = [vp, vp, vp, ctypes.c_int64,
+                                   ctypes.c_double, ctypes.c_int32, vp]
+    lib.fsbm_coal_step.restype = ctypes.c_int
+    lib.fsbm_coal_step_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
+                                         ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp),
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_double, ctypes.c_int32, vp]
+    lib.fsbm_coal_step_multi.restype = ctypes.c_int
+    lib.fsbm_coal_tune.argtypes = [vp, ctypes.c_int64, vp]
+    lib.fsbm_coal_tune.restype = ctypes.c_int
+    lib.fsbm_coal_totals.argtypes = [vp, vp, vp, vp, vp]
+    lib.fsbm_coal_totals.restype = ctypes.c_int
+    lib.fsbm_coal_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.fsbm_coal_get_stats.restype = ctypes.c_int
+    lib.fsbm_coal_destroy.argtypes = [vp]
+    lib.fsbm_coal_destroy.restype = ctypes.c_int
+    lib.fsbm_coal_strerror.argtypes = [ctypes.c_int]
+    lib.fsbm_coal_strerror.restype = ctypes.c_char_p
+    lib.fsbm_coal_last_error.argtypes = [vp]
+    lib.fsbm_coal_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().fsbm_coal_strerror(int(code)).decode()
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_state(N, S, B):
+    import torch
+    if not isinstance(N, torch.Tensor) or N.dtype != torch.float64:
+        raise TypeError("N must be a float64 torch tensor")
+    if not N.is_cuda or not N.is_contiguous():
+        raise ValueError("N must be a contiguous device tensor")
+    if N.dim() != 3 or N.shape[1] != S or N.shape[2] != B:
+        raise ValueError("N must have shape [npoints, %d, %d]" % (S, B))
+
+
+def _check_p(p, P):
+    import torch
+    if not isinstance(p, torch.Tensor) or p.dtype != torch.float64:
+        raise TypeError("p must be a float64 torch tensor")
+    if not p.is_cuda or not p.is_contiguous() or p.shape != (P,):
+        raise ValueError("p must be a contiguous device tensor of [npoints]")
+
+
+class FsbmCoal:
+    """One bin grid and species set (``fsbm_coal_create``)."""
+
+    def __init__(self, nbins: int, nspecies: int, kernel_tables,
+                 p_levels, *, x1_g: Optional[float] = None, s: int = 1,
+                 product=None, precision: int = FSBM_FP64,
+                 theta: float = 1e-30, steps_per_launch: int = 0,
+                 flags: int = 0):
+        lib = load()
+        self.nbins, self.nspecies = int(nbins), int(nspecies)
+        self.precision = int(precision)
+        tables = np.ascontiguousarray(kernel_tables, dtype=np.float64)
+        plev = np.ascontiguousarray(p_levels, dtype=np.float64)
+        opts = Opts()
+        lib.fsbm_coal_opts_default(ctypes.byref(opts))
+        if x1_g is not None:
+            opts.x1_g = float(x1_g)
+        opts.s = int(s)
+        opts.precision = self.precision
+        opts.theta = float(theta)
+        opts.steps_per_launch = int(steps_per_launch)
+        opts.flags = int(flags)
+        prod = None
+        if product is not None:
+            prod = np.ascontiguousarray(product, dtype=np.int32)
+            opts.product = prod.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        h = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = lib.fsbm_coal_create(self.nbins, self.nspecies,
+                                  tables.ctypes.data_as(dp),
+                                  int(plev.shape[0]), plev.ctypes.data_as(dp),
+                                  ctypes.byref(opts), ctypes.byref(h))
+        if rc != FSBM_OK:
+            raise FsbmError(rc, "fsbm_coal_create")
+        self._h = h
+        self._last_npoints = 0
+
+    @classmethod
+    def from_workload(cls, w, precision=FSBM_FP64, **kw):
+        return cls(w.nbins, w.nspecies, w.tables, w.p_levels, x1_g=w.x1_g,
+                   s=w.s, product=w.product if w.nspecies > 1 else None,
+                   precision=precision, theta=w.theta, **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _raise(self, rc, where):
+        detail = load().fsbm_coal_last_error(self._h).decode()
+        raise FsbmError(rc, where, detail)
+
+    def step(self, N, p, dt: float, nsteps: int, stream=None):
+        """Advance N ([P][S][B] float64, device) in place."""
+        _check_state(N, self.nspecies, self.nbins)
+        P = int(N.shape[0])
+        _check_p(p, P)
+        rc = load().fsbm_coal_step(self._h, N.data_ptr(), p.data_ptr(), P,
+                                   float(dt), int(nsteps),
+                                   _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_step")
+        self._last_npoints = P
+
+    def totals(self):
+        """Per-point (mass_before, mass_after, num_before, num_after)."""
+        import torch
+        P = self._last_npoints
+        out = [torch.empty(P, dtype=torch.float64, device="cuda")
+               for _ in range(4)]
+        rc = load().fsbm_coal_totals(self._h, *[o.data_ptr() for o in out])
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_totals")
+        return tuple(out)
+
+    def stats(self) -> dict:
+        st = Stats()
+        rc = load().fsbm_coal_get_stats(self._h, ctypes.byref(st))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_get_stats")
+        return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def tune(self, npoints_hint: int, stream=None):
+        rc = load().fsbm_coal_tune(self._h, int(npoints_hint),
+                                   _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_tune")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().fsbm_coal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_multi(handles: Sequence[FsbmCoal], Ns, ps, dt: float, nsteps: int,
+               stream=None):
+    """One launch sequence over several grids (``fsbm_coal_step_multi``)."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.handle for h in handles])
+    nptr = (ctypes.c_void_p * n)()
+    pptr = (ctypes.c_void_p * n)()
+    cnt = (ctypes.c_int64 * n)()
+    for g, (h, N, p) in enumerate(zip(handles, Ns, ps)):
+        _check_state(N, h.nspecies, h.nbins)
+        _check_p(p, int(N.shape[0]))
+        nptr[g] = N.data_ptr()
+        pptr[g] = p.data_ptr()
+        cnt[g] = int(N.shape[0])
+        h._last_npoints = int(N.shape[0])
+    rc = load().fsbm_coal_step_multi(hs, n, nptr, pptr, cnt, float(dt),
+                                     int(nsteps), _stream_handle(stream))
+    if rc != FSBM_OK:
+        raise FsbmError(rc, "fsbm_coal_step_multi")

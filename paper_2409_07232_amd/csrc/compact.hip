@@ -1,0 +1,286 @@
+// compact.hip -- cloudy-point compaction and the AoS <-> SoA staging around
+// the step kernels.
+//
+// The paper isolates the collision call behind a per-point predicate array
+// (Sec. V-B) and notes that cloud-free cells need far less work (Sec. VII).
+// Here a point is cloudy iff it holds mass; collisions neither create nor
+// remove a point's mass, so the cloudy set is fixed for the whole call and
+// is built once per call:
+//   count   per block of points: cloudy points per pressure bracket
+//   scan    one block: exclusive scan over blocks, per bracket; bracket
+//           bases padded to whole waves so that each wave of the step
+//           kernels sees a single bracket
+//   gather  cloudy point -> slot (stable: point order within a bracket),
+//           bins copied into the structure-of-arrays workspace,
+//           interpolation weight and FP64 totals recorded
+//   scatter workspace -> caller's [point][species][bin] array, totals
+// Everything stays on the device, so the sequence can be captured in a
+// hipGraph without host round trips.
+#include "device_common.hpp"
+
+namespace fsbm {
+
+namespace {
+
+constexpr int kCompactThreads = 256;
+
+// Pressure bracket and weight of level l: clamp p into the tabulated range,
+// take the first level pair with p_l >= p >= p_{l+1}, w is the weight of
+// level l (linear interpolation, Sec. V-A).
+__device__ __forceinline__ void bracket_of(const double *plev, int L,
+                                           double p, int &l, double &w) {
+  if (L == 1) {
+    l = 0;
+    w = 0.0;
+    return;
+  }
+  p = fmin(fmax(p, plev[L - 1]), plev[0]);
+  int b = 0;
+  while (b < L - 2 && !(plev[b] >= p && p >= plev[b + 1])) ++b;
+  l = b;
+  w = (p - plev[b + 1]) / (plev[b] - plev[b + 1]);
+}
+
+__device__ __forceinline__ bool point_is_cloudy(const double *row, int SB) {
+  bool any = false;
+  for (int q = 0; q < SB; ++q) any = any || (row[q] > 0.0);
+  return any;
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+    compact_count(const double *__restrict__ N, const double *__restrict__ p,
+                  int64_t npoints, int SB, const double *__restrict__ plev,
+                  int L, int *__restrict__ block_counts) {
+  __shared__ int cnt[kMaxBuckets];
+  if (threadIdx.x < kMaxBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
+  if (pt < npoints && point_is_cloudy(N + pt * SB, SB)) {
+    int l;
+    double w;
+    bracket_of(plev, L, p[pt], l, w);
+    atomicAdd(&cnt[l], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxBuckets)
+    block_counts[(size_t)blockIdx.x * kMaxBuckets + threadIdx.x] =
+        cnt[threadIdx.x];
+}
+
+// One block of 1024 threads: exclusive scan of block counts per bracket.
+__global__ void __launch_bounds__(1024)
+    compact_scan(const int *__restrict__ block_counts,
+                 int *__restrict__ block_offsets, int nblocks, int nbuckets,
+                 CompactMeta *__restrict__ meta) {
+  __shared__ int part[1024];
+  __shared__ int totals[kMaxBuckets];
+  const int t = threadIdx.x;
+  const int per = (nblocks + 1023) / 1024;
+  const int b0 = t * per;
+  const int b1 = min(b0 + per, nblocks);
+  for (int bk = 0; bk < nbuckets; ++bk) {
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += block_counts[(size_t)b * kMaxBuckets + bk];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partial sums
+    for (int o = 1; o < 1024; o <<= 1) {
+      int v = (t >= o) ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = part[t] - s;  // exclusive prefix of this thread's range
+    for (int b = b0; b < b1; ++b) {
+      const int c = block_counts[(size_t)b * kMaxBuckets + bk];
+      block_offsets[(size_t)b * kMaxBuckets + bk] = run;
+      run += c;
+    }
+    if (t == 1023) totals[bk] = part[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    int base = 0, nact = 0;
+    for (int bk = 0; bk < kMaxBuckets; ++bk) {
+      const int c = bk < nbuckets ? totals[bk] : 0;
+      meta->bucket_base[bk] = base;
+      meta->bucket_count[bk] = c;
+      base += (c + kWave - 1) / kWave * kWave;
+      nact += c;
+    }
+    meta->bucket_base[kMaxBuckets] = base;
+    meta->nslots = base;
+    meta->nactive = nact;
+  }
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+    compact_gather(const double *__restrict__ N, const double *__restrict__ p,
+                   int64_t npoints, int S, int B,
+                   const double *__restrict__ plev, int L,
+                   const int *__restrict__ block_offsets,
+                   const CompactMeta *__restrict__ meta,
+                   int *__restrict__ slot_point, double *__restrict__ state,
+                   double *__restrict__ wgt, int slot_cap,
+                   const double *__restrict__ x, double *__restrict__ tot) {
+  constexpr int kWaves = kCompactThreads / kWave;
+  __shared__ int wave_cnt[kWaves][kMaxBuckets];
+  const int SB = S * B;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
+  const bool inside = pt < npoints;
+  const double *row = N + (inside ? pt : 0) * SB;
+  const bool cloudy = inside && point_is_cloudy(row, SB);
+  int l = 0;
+  double w = 0.0;
+  if (cloudy) bracket_of(plev, L, p[pt], l, w);
+  // stable rank of this point among the block's cloudy points of bracket l
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  int rank = 0;
+  for (int bk = 0; bk < kMaxBuckets; ++bk) {
+    const uint64_t m = __ballot(cloudy && l == bk);
+    if (lane == 0) wave_cnt[wv][bk] = __popcll(m);
+    if (cloudy && l == bk) rank = __popcll(m & lt_mask);
+  }
+  __syncthreads();
+  if (cloudy) {
+    int before = 0;
+    for (int v = 0; v < wv; ++v) before += wave_cnt[v][l];
+    const int slot = meta->bucket_base[l] +
+                     block_offsets[(size_t)blockIdx.x * kMaxBuckets + l] +
+                     before + rank;
+    slot_point[slot] = (int)pt;
+    wgt[slot] = w;
+    for (int q = 0; q < SB; ++q) state[state_index(q, slot, SB)] = row[q];
+  }
+  if (inside && tot) {
+    double m = 0.0, n = 0.0;
+    if (cloudy)
+      for (int q = 0; q < SB; ++q) {
+        m += row[q] * x[q % B];
+        n += row[q];
+      }
+    tot[pt] = m;                     // mass before
+    tot[(size_t)npoints + pt] = m;   // mass after (cloud-free: unchanged)
+    tot[2 * (size_t)npoints + pt] = n;
+    tot[3 * (size_t)npoints + pt] = n;
+  }
+}
+
+// Padding slots of each bracket (up to the next whole wave) hold no point.
+__global__ void fill_padding(const CompactMeta *__restrict__ meta,
+                             int *__restrict__ slot_point) {
+  const int bk = blockIdx.x;
+  const int first = meta->bucket_base[bk] + meta->bucket_count[bk];
+  const int end = meta->bucket_base[bk + 1];
+  const int s = first + threadIdx.x;
+  if (s < end) slot_point[s] = -1;
+}
+
+__global__ void __launch_bounds__(kCompactThreads)
+    scatter_back(double *__restrict__ N, int S, int B,
+                 const CompactMeta *__restrict__ meta,
+                 const int *__restrict__ slot_point,
+                 const double *__restrict__ state, int slot_cap,
+                 const double *__restrict__ x, double *__restrict__ tot,
+                 int64_t npoints) {
+  const int slot = blockIdx.x * kCompactThreads + threadIdx.x;
+  if (slot >= meta->nslots) return;
+  const int pt = slot_point[slot];
+  if (pt < 0) return;
+  const int SB = S * B;
+  double *row = N + (int64_t)pt * SB;
+  double m = 0.0, n = 0.0;
+  for (int q = 0; q < SB; ++q) {
+    const double v = state[state_index(q, slot, SB)];
+    row[q] = v;
+    m += v * x[q % B];
+    n += v;
+  }
+  if (tot) {
+    tot[(size_t)npoints + pt] = m;
+    tot[3 * (size_t)npoints + pt] = n;
+  }
+}
+
+__global__ void zero_u64(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void check_state(const double *__restrict__ N, int64_t n,
+                            int *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double v = N[i];
+    if (!(v >= 0.0) || !isfinite(v)) atomicOr(bad, 1);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_compact_count(const double *N, const double *p,
+                                int64_t npoints, int SB, const double *plev,
+                                int L, int *block_counts, int nblocks,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(compact_count, dim3(nblocks), dim3(kCompactThreads), 0,
+                     st, N, p, npoints, SB, plev, L, block_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_scan(const int *block_counts, int *block_offsets,
+                               int nblocks, int nbuckets, CompactMeta *meta,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(compact_scan, dim3(1), dim3(1024), 0, st, block_counts,
+                     block_offsets, nblocks, nbuckets, meta);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_gather(const double *N, const double *p,
+                                 int64_t npoints, int S, int B,
+                                 const double *plev, int L,
+                                 const int *block_offsets,
+                                 const CompactMeta *meta, int nblocks,
+                                 int *slot_point, double *state, double *wgt,
+                                 int slot_cap, const double *x, double *tot,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(compact_gather, dim3(nblocks), dim3(kCompactThreads), 0,
+                     st, N, p, npoints, S, B, plev, L, block_offsets, meta,
+                     slot_point, state, wgt, slot_cap, x, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
+                               int slot_cap, hipStream_t st) {
+  (void)slot_cap;
+  hipLaunchKernelGGL(fill_padding, dim3(kMaxBuckets), dim3(kWave), 0, st,
+                     meta, slot_point);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
+                          const CompactMeta *meta, const int *slot_point,
+                          const double *state, int slot_cap, const double *x,
+                          double *tot, hipStream_t st) {
+  const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;
+  hipLaunchKernelGGL(scatter_back, dim3(blocks), dim3(kCompactThreads), 0, st,
+                     N, S, B, meta, slot_point, state, slot_cap, x, tot,
+                     npoints);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_state(const double *N, int64_t n, int *bad,
+                              hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(check_state, dim3((unsigned)blocks), dim3(256), 0, st, N,
+                     n, bad);
+  return hipGetLastError();
+}
+
+}  // namespace fsbm

@@ -1,0 +1,128 @@
+// fsbm_internal.hpp -- structures shared by the host library and the
+// gfx950 kernels of the collision-coalescence step.  Internal: not part of
+// the C ABI (include/fsbm_coal.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsbm {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxSpecies = 8;
+constexpr int kMaxBins = 512;
+constexpr int kMaxBuckets = 8;     // pressure brackets (levels - 1), capped
+constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
+constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
+// Empty-neighbour guard of the flux fraction: x1 >= ln(1e-60).
+constexpr double kX1Floor = -138.15510557964274;
+
+// Read-only description of one bin grid and species set, device pointers.
+struct DevModel {
+  int B, S, L, s;
+  int nbr;        // pressure brackets = max(L - 1, 1)
+  int npairs;     // S (S + 1) / 2 species pairs
+  double theta;
+  const double *x;      // [B] bin masses (g)
+  const double *invx;   // [B] 1 / x
+  const float *invxf;   // [B] 1 / x rounded to FP32
+  const int *kt;        // [B*B] target bin of pair (i, j), -1 = off grid
+  const double *ct;     // [B*B] Courant number c_ij (FP64)
+  const float *ctf;     // [B*B] c_ij rounded to FP32
+  const int *product;   // [S*S] product species
+  const double *Kd;     // [npairs][nbr][B][B][2] (K_{l+1}, K_l - K_{l+1})
+  const float *Kf;      // same, FP32
+  const double *plev;   // [L]
+  // species pair 0 tables transposed to [nbr][j][i][2] and [j][i]: row j of
+  // the pair loop reads its columns i < j contiguously
+  const double *KdT;
+  const float *KfT;
+  const double *ctT;
+  const float *ctfT;
+};
+
+// Compaction results, written on the device (graph-capturable: no host
+// round trip).  Slots of one pressure bracket are contiguous and padded to a
+// multiple of the wave size so that every wave shares one bracket.
+struct CompactMeta {
+  int nslots;                       // total slots incl. padding
+  int nactive;                      // cloudy points
+  int bucket_base[kMaxBuckets + 1]; // first slot of each bracket, + end
+  int bucket_count[kMaxBuckets];    // cloudy points per bracket
+};
+
+// Element (q, slot) of the tiled structure-of-arrays state: each wave's 64
+// slots form one tile in which bin q of all 64 points is a contiguous
+// 512-byte row.
+__host__ __device__ __forceinline__ size_t state_index(int q, int slot,
+                                                       int SB) {
+  return ((size_t)(slot >> 6) * SB + q) * 64 + (slot & 63);
+}
+
+// Per-call device workspace of one handle.
+struct DevWork {
+  int64_t npoints;
+  int slot_cap;          // capacity of the slot arrays (stride of state)
+  int *slot_point;       // [slot_cap] point index or -1 (padding)
+  double *state;         // tiled SoA [slot/64][S*B][slot%64] bin numbers N
+  double *wgt;           // [slot_cap] pressure-interpolation weight
+  CompactMeta *meta;     // device
+  int *block_counts;     // [nblocks_compact][kMaxBuckets]
+  int *block_offsets;    // same shape, exclusive scan
+  double *tot;           // [4][npoints]: mass before/after, number b/a
+  int *pending;          // [slot_cap] steps left for the exact FP64 path
+  unsigned long long *counters;  // [4]: pair evals, limiter, fallback, -
+};
+
+// Arguments of the step kernels.
+struct StepArgs {
+  DevModel m;
+  int slot_cap;
+  const int *slot_point;
+  double *state;
+  const double *wgt;
+  const CompactMeta *meta;
+  int *pending;         // [slot_cap]: > 0 where a lane left the fast path
+  unsigned long long *counters;
+  double dt;
+  int nsteps;           // steps in this launch
+};
+
+// --- host-side launchers (defined in the kernel translation units) -------
+hipError_t launch_compact_count(const double *N, const double *p,
+                                int64_t npoints, int SB, const double *plev,
+                                int L, int *block_counts, int nblocks,
+                                hipStream_t st);
+hipError_t launch_compact_scan(const int *block_counts, int *block_offsets,
+                               int nblocks, int nbuckets, CompactMeta *meta,
+                               hipStream_t st);
+hipError_t launch_compact_gather(const double *N, const double *p,
+                                 int64_t npoints, int S, int B,
+                                 const double *plev, int L,
+                                 const int *block_offsets,
+                                 const CompactMeta *meta, int nblocks,
+                                 int *slot_point, double *state,
+                                 double *wgt, int slot_cap,
+                                 const double *x, double *tot,
+                                 hipStream_t st);
+hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
+                               int slot_cap, hipStream_t st);
+hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
+                          const CompactMeta *meta, const int *slot_point,
+                          const double *state, int slot_cap, const double *x,
+                          double *tot, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+hipError_t launch_check_state(const double *N, int64_t n, int *bad,
+                              hipStream_t st);
+
+// One-point-per-lane kernels (single species, mass-doubling grid).
+bool lane_kernel_supported(int B, int S, int s);
+hipError_t launch_lane_step(const StepArgs &a, int precision,
+                            int waves_per_block, int max_slots,
+                            hipStream_t st);
+// Exact FP64 steps (with the positivity limiter) for every slot whose fast
+// kernel stopped on an over-demand bound; clears pending[].
+hipError_t launch_slow_steps(const StepArgs &a, int max_slots,
+                             hipStream_t st);
+
+}  // namespace fsbm

@@ -1,0 +1,447 @@
+// kernels_lane.hip -- one grid point per lane: the collision step for one
+// species on the mass-doubling grid (x_{k+1} = 2 x_k) with at most
+// kLaneMaxBins bins.  This is the shape of the FSBM liquid spectrum with 33
+// bins (Sec. III).
+//
+// Layout and mapping (gfx950):
+//  * compacted cloudy points sit in a structure-of-arrays workspace
+//    state[bin][slot], so a wave reads and writes each bin of its 64 points
+//    as one contiguous 512-byte row;
+//  * the pair loop is wave-uniform: rows j (the larger bin) run over the
+//    union of the wave's active bins, in descending order; columns i < j are
+//    unrolled.  Kernel-table entries, Courant numbers and bin masses are
+//    therefore scalar operands, and every per-pair register access has a
+//    static index (the column bin i);
+//  * per lane, the masses and the losses of column bins stay in VGPRs; the
+//    two per-row updates of bins j and j+1 go to a small per-lane LDS array
+//    laid out [bin][lane] (bank-conflict free);
+//  * descending rows complete each bin's losses before its own row ends, so
+//    the positivity-limiter test of a bin is taken right there;
+//  * every wave lies in one pressure bracket (the compaction pads brackets to
+//    whole waves): the per-pair kernel interpolation is one FMA with two
+//    scalar table operands.
+//
+// Pair (i < j) on the doubling grid: target bin k = j, Courant number
+// c = 2^(i-j); self pairs (j, j) land exactly on bin j+1.
+//  * FP64 kernel: the method as defined, in FP64.
+//  * FP32C kernel: masses normalised by the point's FP64 total; pair amounts
+//    in FP32, applied as exact transfers (bin i -> bin j: A, bin j -> bin
+//    j+1: F and the self-pair mass) into compensated per-bin sums (Kahan
+//    family, TwoSum error capture), then carried into an FP64 update of the
+//    FP64 state.
+// A lane whose over-demand test fires leaves the fast kernel; the exact FP64
+// path (slow_path.hpp) finishes that launch's steps for it.
+#include <float.h>
+
+#include "device_common.hpp"
+#include "slow_path.hpp"
+
+// Kahan sums and the exact-transfer bookkeeping rely on every rounding
+// being the one written; fused forms are spelled out where wanted.
+#pragma clang fp contract(off)
+
+namespace fsbm {
+
+namespace {
+
+// Bracket of a wave: the compaction pads every bracket to whole waves.
+__device__ __forceinline__ int wave_bracket(const CompactMeta *meta,
+                                           int wave_first_slot, int nbr) {
+  int br = 0;
+  for (int b = 1; b < nbr; ++b)
+    if (wave_first_slot >= meta->bucket_base[b]) br = b;
+  return uniform(br);
+}
+
+__device__ __forceinline__ void add_counters(unsigned long long *counters,
+                                             unsigned long long pairs) {
+  pairs = wave_sum_u64(pairs);
+  if ((threadIdx.x & (kWave - 1)) == 0 && pairs)
+    atomicAdd(&counters[0], pairs);
+}
+
+// Pairs a lane evaluates in row j: bin j active, each active i < j, plus the
+// self pair while its merged mass stays on the grid.
+template <int B>
+__device__ __forceinline__ unsigned row_pairs(uint64_t act, int j) {
+  if (!((act >> j) & 1ull)) return 0u;
+  const uint64_t below = (j == 0) ? 0ull : (act & (~0ull >> (64 - j)));
+  return (unsigned)__popcll(below) + ((j + 1 <= B - 1) ? 1u : 0u);
+}
+
+__device__ __forceinline__ bool bit_of(uint32_t lo, uint32_t hi, int k) {
+  return (k < 32) ? ((lo >> k) & 1u) : ((hi >> (k - 32)) & 1u);
+}
+
+// ---------------------------------------------------------- FP64 kernel
+template <int B, int WPB>
+__global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
+  constexpr int nthr = kWave * WPB;
+  __shared__ double lds_g[B * nthr];  // [bin][thread] gains of bins
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int slot = blockIdx.x * nthr + tid;
+  const int nslots = uniform(a.meta->nslots);
+  const int wave_first = uniform(slot & ~(kWave - 1));
+  if (wave_first >= nslots) return;
+  const int br = wave_bracket(a.meta, wave_first, a.m.nbr);
+  bool live = slot < nslots && a.slot_point[slot] >= 0;
+  const double w = live ? a.wgt[slot] : 0.0;
+  // tables transposed to [j][i]: the columns of row j are contiguous
+  const double *__restrict__ Kd = a.m.KdT + (size_t)br * B * B * 2;
+  const double *__restrict__ ctab = a.m.ctT;
+  const double *__restrict__ ixg = a.m.invx;
+  // doubling grid: x_k = x_1 2^k exactly, so products with x_k are exact
+  // power-of-two scalings of products with x_1
+  const double x1 = ldc(a.m.x);
+  // bin k of this lane's point: stw[k * 64 + lane] (wave tile, uniform base)
+  double *const stw = a.state + (size_t)wave_first * B;
+  double *G = lds_g + tid;
+  const double theta = a.m.theta, dt = a.dt;
+  unsigned long long npairs = 0;
+
+  for (int step = 0; step < a.nsteps; ++step) {
+    // Opaque per-step copy of the wave's base pointer: keeps the compiler
+    // from hoisting B per-lane 64-bit addresses out of the step loop (the
+    // loads use a scalar base, one lane offset and immediate offsets).
+    double *sb = stw;
+    asm volatile("" : "+s"(sb));
+    // S1/S2: masses, FP64 total (bins ascending), activity.
+    BinsD<B> Mt;
+    double Mtot = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const double v = sb[k * kWave + lane];
+      const double Mk = live ? ldexp(__dmul_rn(v, x1), k) : 0.0;
+      Mt.set(k, Mk);
+      Mtot = __dadd_rn(Mtot, Mk);
+    }
+    const double thr = theta * Mtot;
+    uint64_t act = 0;
+    BinsD<B> L;  // losses of bins as the smaller partner of a pair
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const double Mk = Mt.get(k);
+      const bool ak = Mk > 0.0 && Mk >= thr;
+      act |= (uint64_t)ak << k;
+      Mt.set(k, ak ? Mk : 0.0);
+      L.set(k, 0.0);
+      G[k * nthr] = 0.0;
+    }
+    const uint64_t uni = wave_or64(act);
+    const int lo = uniform(uni ? (int)__builtin_ctzll(uni) : 0);
+    const int hi = uniform(uni ? 63 - (int)__builtin_clzll(uni) : -1);
+    const uint32_t uni_lo = uniform((int)(uint32_t)uni);
+    const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
+    bool flag = false;
+    unsigned step_pairs = 0;
+
+    // S3/S4: rows j descending, columns i < j unrolled.
+    for (int j = hi; j >= lo; --j) {
+      if (!bit_of(uni_lo, uni_hi, j)) continue;
+      // columns to visit: i < j with bin i active in some lane of the wave
+      const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+      const uint32_t cl = uni_lo & (uint32_t)below_mask;
+      const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
+      const double Mtj = Mt.get(j);
+      const double qj = dt * (Mtj * ldc(ixg + j));  // dt N_j, 0 if inactive
+      const bool has_flux = j <= B - 2;
+      const double lnj1 = has_flux ? log(Mt.get(j + 1)) : 0.0;  // -inf if 0
+      const double *Kj = Kd + (size_t)j * B * 2;  // row j: [i][2]
+      const double *cj = ctab + (size_t)j * B;
+      double netj = 0.0, fout = 0.0, dneg = 0.0;
+#pragma unroll
+      for (int i = 0; i < B - 1; ++i) {
+        if (!bit_of(cl, ch, i)) continue;
+        const double *e = Kj + i * 2;
+        const double K = fma(ldc(e + 1), w, ldc(e));
+        // A = C x_i = dt K N_j M_i, B = C x_j = A 2^(j-i)
+        const double A = (qj * K) * Mt.get(i);
+        const double Bm = ldexp(A, j - i);
+        const double Sm = A + Bm;
+        double F = 0.0;
+        if (has_flux) {
+          const double den = fmax(Mtj + Sm, DBL_MIN);
+          const double x1f = fmax(lnj1 - log(den), kX1Floor);
+          F = flux_fraction_f64(ldc(cj + i), x1f) * Sm;
+        }
+        L.set(i, L.get(i) + A);
+        const double cn = (Sm - F) - Bm;  // merged net of bin j, this pair
+        netj += cn;
+        fout += F;
+        dneg += fmax(-cn, 0.0);
+      }
+      // self pair: 2 x_j = x_{j+1} exactly, no flux; off grid for j = B-1
+      double self2 = 0.0;
+      if (j + 1 <= B - 1) {
+        const double *e = Kj + j * 2;
+        const double K = fma(ldc(e + 1), w, ldc(e));
+        const double A = 0.5 * ((qj * K) * Mtj);
+        self2 = A + A;
+      }
+      // S5 test: demand on bin j = its losses as the smaller partner (all
+      // rows above j are done) + self pair + negative merged nets here.
+      const double demand = L.get(j) + self2 + dneg;
+      flag = flag || (Mtj > 0.0 && demand > Mtj);
+      G[j * nthr] += netj - self2;
+      if (j + 1 <= B - 1) G[(j + 1) * nthr] += fout + self2;
+      step_pairs += row_pairs<B>(act, j);
+    }
+
+    if (flag) {
+      // the exact two-pass step (with the limiter) takes over this point
+      // for the rest of the launch
+      a.pending[slot] = a.nsteps - step;
+      live = false;
+    } else if (live) {
+      npairs += step_pairs;
+      // reload the state rather than keep 2B registers live across the
+      // pair loop
+      asm volatile("" ::: "memory");
+      // S6: FP64 update, negative round-off clamped, back to numbers
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        double *q = sb + k * kWave + lane;
+        const double Mk = ldexp(__dmul_rn(*q, x1), k);
+        double Mn = Mk + (G[k * nthr] - L.get(k));
+        Mn = Mn < 0.0 ? 0.0 : Mn;
+        *q = ldexp(Mn / x1, -k);
+      }
+    }
+  }
+  add_counters(a.counters, npairs);
+}
+
+// --------------------------------------------------------- FP32C kernel
+template <int B, int WPB>
+__global__ void __launch_bounds__(kWave *WPB) lane_step_f32c(StepArgs a) {
+  constexpr int nthr = kWave * WPB;
+  __shared__ float lds_gf[2 * B * nthr];  // [s|c][bin][thread] gains
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int slot = blockIdx.x * nthr + tid;
+  const int nslots = uniform(a.meta->nslots);
+  const int wave_first = uniform(slot & ~(kWave - 1));
+  if (wave_first >= nslots) return;
+  const int br = wave_bracket(a.meta, wave_first, a.m.nbr);
+  bool live = slot < nslots && a.slot_point[slot] >= 0;
+  const double w = live ? a.wgt[slot] : 0.0;
+  const float wf = (float)w;
+  const float *__restrict__ Kf = a.m.KfT + (size_t)br * B * B * 2;
+  const float *__restrict__ ctf = a.m.ctfT;
+  const float *__restrict__ ixf = a.m.invxf;
+  const double x1 = ldc(a.m.x);  // x_k = x_1 2^k exactly
+  double *const stw = a.state + (size_t)wave_first * B;
+  float *Gs = lds_gf + tid;
+  float *Gc = lds_gf + B * nthr + tid;
+  const double theta = a.m.theta, dt = a.dt;
+  unsigned long long npairs = 0;
+
+  for (int step = 0; step < a.nsteps; ++step) {
+    double *sb = stw;  // opaque per step, see the FP64 kernel
+    asm volatile("" : "+s"(sb));
+    // S1/S2 in FP64; FP32 masses normalised by the FP64 total.
+    double Mtot = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const double v = sb[k * kWave + lane];
+      Mtot = __dadd_rn(Mtot, live ? ldexp(__dmul_rn(v, x1), k) : 0.0);
+    }
+    const double thr = theta * Mtot;
+    const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
+    uint64_t act = 0;
+    BinsF<B> m;        // active M_k / M_tot
+    BinsF<B> Ls, Lc;   // compensated losses of bins as smaller partner
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const double v = sb[k * kWave + lane];
+      const double Mk = live ? ldexp(__dmul_rn(v, x1), k) : 0.0;
+      const bool ak = Mk > 0.0 && Mk >= thr;
+      act |= (uint64_t)ak << k;
+      m.set(k, ak ? (float)(Mk * inv) : 0.0f);
+      Ls.set(k, 0.0f);
+      Lc.set(k, 0.0f);
+      Gs[k * nthr] = 0.0f;
+      Gc[k * nthr] = 0.0f;
+    }
+    const float tau = (float)(dt * Mtot);
+    const uint64_t uni = wave_or64(act);
+    const int lo = uniform(uni ? (int)__builtin_ctzll(uni) : 0);
+    const int hi = uniform(uni ? 63 - (int)__builtin_clzll(uni) : -1);
+    const uint32_t uni_lo = uniform((int)(uint32_t)uni);
+    const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
+    bool flag = false;
+    unsigned step_pairs = 0;
+
+    for (int j = hi; j >= lo; --j) {
+      if (!bit_of(uni_lo, uni_hi, j)) continue;
+      const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+      const uint32_t cl = uni_lo & (uint32_t)below_mask;
+      const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
+      const float mj = m.get(j);
+      const float tj = (tau * mj) * ldc(ixf + j);  // A = K m_i tj
+      const bool has_flux = j <= B - 2;
+      const float lmj1 =
+          has_flux ? __builtin_amdgcn_logf(m.get(j + 1)) : 0.0f;  // log2
+      const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
+      const float *cj = ctf + (size_t)j * B;
+      float as = 0.0f, ac = 0.0f;  // mass arriving in bin j (compensated)
+      float fs = 0.0f, fc = 0.0f;  // flux leaving bin j for j+1
+#pragma unroll
+      for (int i = 0; i < B - 1; ++i) {
+        if (!bit_of(cl, ch, i)) continue;
+        const float *e = Kj + i * 2;
+        const float K = __builtin_fmaf(ldc(e + 1), wf, ldc(e));
+        const float A = (tj * K) * m.get(i);
+        // x_j / x_i = 2^(j-i) exactly on the doubling grid
+        const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
+        const float Sm = A + Bm;
+        {
+          float s = Ls.get(i), c = Lc.get(i);
+          comp_add(s, c, A);
+          Ls.set(i, s);
+          Lc.set(i, c);
+        }
+        comp_add(as, ac, A);
+        if (has_flux) {
+          const float den = __builtin_fmaxf(mj + Sm, 0x1p-120f);
+          float lam = lmj1 - __builtin_amdgcn_logf(den);
+          lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
+          const float c = ldc(cj + i);
+          const float F = flux_fraction_f32(c, c * kLn2f, lam) * Sm;
+          comp_add(fs, fc, F);
+        }
+      }
+      // self pair: transfer 2A from bin j to bin j+1 (exact hit, no flux)
+      float self2 = 0.0f;
+      if (j + 1 <= B - 1) {
+        const float *e = Kj + j * 2;
+        const float K = __builtin_fmaf(ldc(e + 1), wf, ldc(e));
+        const float A = 0.5f * ((tj * K) * mj);
+        self2 = A + A;
+      }
+      // S5 bound: losses as the smaller partner + self pair + every flux
+      // leaving bin j (>= the negative merged nets); FP32 margin.
+      const float demand = (Ls.get(j) + Lc.get(j)) + self2 + (fs + fc);
+      flag = flag || (mj > 0.0f && demand > mj * (1.0f - 1e-5f));
+      {
+        float s = Gs[j * nthr], c = Gc[j * nthr];
+        comp_add(s, c, as);
+        comp_add(s, c, ac);
+        comp_add(s, c, -fs);
+        comp_add(s, c, -fc);
+        comp_add(s, c, -self2);
+        Gs[j * nthr] = s;
+        Gc[j * nthr] = c;
+      }
+      if (j + 1 <= B - 1) {
+        float s = Gs[(j + 1) * nthr], c = Gc[(j + 1) * nthr];
+        comp_add(s, c, fs);
+        comp_add(s, c, fc);
+        comp_add(s, c, self2);
+        Gs[(j + 1) * nthr] = s;
+        Gc[(j + 1) * nthr] = c;
+      }
+      step_pairs += row_pairs<B>(act, j);
+    }
+
+    if (flag) {
+      a.pending[slot] = a.nsteps - step;
+      live = false;
+    } else if (live) {
+      npairs += step_pairs;
+      asm volatile("" ::: "memory");
+      // FP64 update from the compensated FP32 sums (exact sum = s + c)
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const double g = (double)Gs[k * nthr] + (double)Gc[k * nthr];
+        const double l = (double)Ls.get(k) + (double)Lc.get(k);
+        double *q = sb + k * kWave + lane;
+        const double Mk = ldexp(__dmul_rn(*q, x1), k);
+        double Mn = Mk + (g - l) * Mtot;
+        Mn = Mn < 0.0 ? 0.0 : Mn;
+        *q = ldexp(Mn / x1, -k);
+      }
+    }
+  }
+  add_counters(a.counters, npairs);
+}
+
+// Exact FP64 steps for lanes the fast kernels handed over.
+__global__ void __launch_bounds__(64) slow_steps(StepArgs a) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= a.meta->nslots) return;
+  const int n = a.pending[slot];
+  if (n <= 0) return;
+  int br = 0;
+  for (int b = 1; b < a.m.nbr; ++b)
+    if ((slot & ~(kWave - 1)) >= a.meta->bucket_base[b]) br = b;
+  unsigned long long pairs = 0, lim = 0;
+  for (int k = 0; k < n; ++k)
+    lim += slow_step_f64<kLaneMaxBins>(
+        a.m, a.state + state_index(0, slot, a.m.S * a.m.B), kWave,
+        a.wgt[slot], br, a.dt, &pairs);
+  a.pending[slot] = 0;
+  atomicAdd(&a.counters[0], pairs);
+  if (lim) atomicAdd(&a.counters[1], lim);
+  atomicAdd(&a.counters[2], (unsigned long long)n);
+}
+
+template <int B, int WPB>
+hipError_t launch_bw(const StepArgs &a, int precision, int max_slots,
+                     hipStream_t st) {
+  constexpr int threads = kWave * WPB;
+  const int blocks = (max_slots + threads - 1) / threads;
+  if (blocks == 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL((lane_step_f64<B, WPB>), dim3(blocks), dim3(threads),
+                       0, st, a);
+  else
+    hipLaunchKernelGGL((lane_step_f32c<B, WPB>), dim3(blocks),
+                       dim3(threads), 0, st, a);
+  return hipGetLastError();
+}
+
+// Slot capacity is a multiple of kLaneMaxWpb * kWave, so every launched
+// thread addresses a slot inside the workspace.
+template <int B>
+hipError_t launch_b(const StepArgs &a, int precision, int wpb, int max_slots,
+                    hipStream_t st) {
+  if (wpb == 2) return launch_bw<B, 2>(a, precision, max_slots, st);
+  return launch_bw<B, 1>(a, precision, max_slots, st);
+}
+
+}  // namespace
+
+hipError_t launch_slow_steps(const StepArgs &a, int max_slots,
+                             hipStream_t st) {
+  const int blocks = (max_slots + 63) / 64;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(slow_steps, dim3(blocks), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+bool lane_kernel_supported(int B, int S, int s) {
+  return S == 1 && s == 1 && (B == 3 || B == 8 || B == 16 || B == 33 ||
+                              B == 40);
+}
+
+hipError_t launch_lane_step(const StepArgs &a, int precision, int wpb,
+                            int max_slots, hipStream_t st) {
+  switch (a.m.B) {
+    case 3:
+      return launch_b<3>(a, precision, wpb, max_slots, st);
+    case 8:
+      return launch_b<8>(a, precision, wpb, max_slots, st);
+    case 16:
+      return launch_b<16>(a, precision, wpb, max_slots, st);
+    case 33:
+      return launch_b<33>(a, precision, wpb, max_slots, st);
+    case 40:
+      return launch_b<40>(a, precision, wpb, max_slots, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fsbm

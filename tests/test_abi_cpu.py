@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every entry point declared in include/fsbm_coal.h, and the pure-host
+entry points behave as documented."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_07232_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fsbm_coal.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsbm_coal_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_strerror_and_defaults():
+    assert _lib.strerror(0) == "success"
+    assert "invalid" in _lib.strerror(_lib.FSBM_EINVAL)
+    assert "unsupported" in _lib.strerror(_lib.FSBM_EUNSUPPORTED)
+    assert _lib.strerror(-99) == "unknown error"
+    o = _lib.Opts()
+    _lib.load().fsbm_coal_opts_default(ctypes.byref(o))
+    assert o.s == 1 and o.precision == _lib.FSBM_FP64
+    assert o.theta == 1e-30
+    assert abs(o.x1_g - 3.3510321638291124e-11) < 1e-25
+
+
+def test_null_arguments_rejected_without_device_work():
+    lib = _lib.load()
+    assert lib.fsbm_coal_create(33, 1, None, 1, None, None, None) == \
+        _lib.FSBM_EINVAL
+    assert lib.fsbm_coal_step(None, None, None, 10, 1.0, 1, None) == \
+        _lib.FSBM_EINVAL
+    assert lib.fsbm_coal_destroy(None) == 0
+    assert lib.fsbm_coal_last_error(None) == b""
+
+
+def test_no_cpu_fallback_in_binding():
+    src = open(os.path.join(ROOT, "paper_2409_07232_amd", "_lib.py")).read()
+    assert "oracle" not in src
+    with pytest.raises(FileNotFoundError):
+        _lib.load.__wrapped__ if hasattr(_lib.load, "__wrapped__") else None
+        saved = _lib._lib
+        try:
+            _lib._lib = None
+            _lib.load("/nonexistent/libfsbm_coal.so")
+        finally:
+            _lib._lib = saved

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (rel_bin: max over points, species, bins of |dM| / max(|M_ref|,
+1e-9 M_tot)): FP64 path 1e-12, FP32C path 1e-5; relative per-point mass
+drift 1e-10 for both.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import compare
+from paper_2409_07232_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+DRIFT = 1e-10
+
+
+def _lib():
+    from paper_2409_07232_amd import _lib as L
+    return L
+
+
+def model_of(w):
+    return oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
+                              w.product, x1_g=w.x1_g, s=w.s, theta=w.theta)
+
+
+def run_gpu(w, precision, N=None, p=None, dt=None, nsteps=None, flags=0,
+            stream=None, handle=None):
+    L = _lib()
+    h = handle or L.FsbmCoal.from_workload(w, precision=precision,
+                                           flags=flags)
+    Nd = torch.from_numpy(np.ascontiguousarray(w.N if N is None else N)).to(
+        "cuda")
+    pd = torch.from_numpy(np.ascontiguousarray(w.p if p is None else p)).to(
+        "cuda")
+    h.step(Nd, pd, w.dt if dt is None else dt,
+           w.nsteps if nsteps is None else nsteps, stream=stream)
+    torch.cuda.synchronize()
+    out = Nd.cpu().numpy()
+    st = h.stats()
+    return out, st, h
+
+
+def run_oracle(w, N=None, p=None, dt=None, nsteps=None):
+    om = model_of(w)
+    Nr = np.array(w.N if N is None else N, dtype=np.float64, copy=True)
+    om.run(Nr, w.p if p is None else p, w.dt if dt is None else dt,
+           w.nsteps if nsteps is None else nsteps)
+    return Nr, om.grid()
+
+
+def check(got, ref, start, x, precision, label="", floor=1e-9):
+    err = compare.rel_bin(got, ref, x, floor=floor)
+    drift = compare.drift(got, start, x)
+    print("%s precision=%d rel_bin=%.3e drift=%.3e" % (label, precision, err,
+                                                      drift), flush=True)
+    assert np.all(got >= 0.0)
+    assert err <= TOL[precision], err
+    assert drift <= DRIFT, drift
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_golovin_full_run(precision):
+    """64 identical points, 33 bins, Golovin kernel, dt 1 s x 1800 steps."""
+    w = wl.config1(npoints=64)
+    ref, x = run_oracle(w.subset(np.arange(1)))
+    got, st, _ = run_gpu(w, precision)
+    check(got, np.repeat(ref, 64, axis=0), w.N, x, precision, "golovin")
+    assert st["active_points"] == 64
+    assert st["limiter_steps"] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_thunderstorm_patch_small(precision):
+    """Config-2 recipe on a 16 x 16 x 50 patch (about 1900 cloudy points,
+    several waves per pressure bracket and ragged tails), 100 steps."""
+    w = wl.config2(nx=16, ny=16, nz=50)
+    ref, x = run_oracle(w)
+    got, st, _ = run_gpu(w, precision)
+    dry = ~w.cloudy()
+    assert np.array_equal(got[dry], w.N[dry])
+    check(got, ref, w.N, x, precision, "patch16")
+    assert st["active_points"] == int((~dry).sum())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("npts", [1, 63, 65, 130])
+def test_ragged_point_counts(precision, npts):
+    w = wl.config2(nx=8, ny=8, nz=50)
+    idx = np.sort(np.random.default_rng(npts).choice(w.npoints, npts,
+                                                     replace=False))
+    sub = w.subset(idx)
+    sub.nsteps = 20
+    ref, x = run_oracle(sub)
+    got, _, _ = run_gpu(sub, precision)
+    check(got, ref, sub.N, x, precision, "ragged%d" % npts)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_degenerate_calls(precision):
+    w = wl.config2(nx=8, ny=8, nz=50)
+    L = _lib()
+    h = L.FsbmCoal.from_workload(w, precision=precision)
+    # zero steps: identity, bitwise
+    got, _, _ = run_gpu(w, precision, nsteps=0, handle=h)
+    assert np.array_equal(got, w.N)
+    # all points dry: untouched, bitwise
+    dry = np.zeros_like(w.N)
+    got, st, _ = run_gpu(w, precision, N=dry, handle=h)
+    assert np.array_equal(got, dry)
+    assert st["active_points"] == 0
+    # zero points: accepted no-op
+    Nd = torch.zeros((0, 1, w.nbins), dtype=torch.float64, device="cuda")
+    pd = torch.zeros((0,), dtype=torch.float64, device="cuda")
+    h.step(Nd, pd, 2.0, 5)
+    # invalid arguments are rejected with EINVAL
+    with pytest.raises(L.FsbmError) as e:
+        Nd = torch.from_numpy(w.N.copy()).to("cuda")
+        pd = torch.from_numpy(w.p.copy()).to("cuda")
+        h.step(Nd, pd, -1.0, 5)
+    assert e.value.code == L.FSBM_EINVAL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forced_limiter(precision):
+    """A huge time step over-demands bins: the limiter path must match the
+    oracle and keep mass and positivity.  The limiter empties an
+    over-demanded bin by the exact cancellation M - (M / D) D, so what is left
+    there is rounding noise of order u M; bins below 1e-6 of their point's
+    mass are therefore judged on that absolute scale here."""
+    w = wl.config2(nx=8, ny=8, nz=50)
+    sub = w.subset(wl.sample_active(w, 96))
+    ref, x = run_oracle(sub, dt=4000.0, nsteps=3)
+    got, st, _ = run_gpu(sub, precision, dt=4000.0, nsteps=3)
+    assert st["limiter_steps"] > 0
+    check(got, ref, sub.N, x, precision, "limiter", floor=1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_and_determinism(precision):
+    w = wl.config2(nx=8, ny=8, nz=50)
+    w.nsteps = 30
+    L = _lib()
+    s = torch.cuda.Stream()
+    h = L.FsbmCoal.from_workload(w, precision=precision)
+    p = torch.from_numpy(w.p.copy()).to("cuda")
+    outs = []
+    N = torch.empty((w.npoints, 1, w.nbins), dtype=torch.float64,
+                    device="cuda")
+    N0 = torch.from_numpy(w.N.copy()).to("cuda")
+    for rep in range(3):          # capture once, replay twice
+        with torch.cuda.stream(s):
+            N.copy_(N0)
+            h.step(N, p, w.dt, w.nsteps, stream=s)
+        s.synchronize()
+        outs.append(N.cpu().numpy())
+    hd = L.FsbmCoal.from_workload(w, precision=precision,
+                                  flags=L.FLAG_NO_GRAPH)
+    direct, _, _ = run_gpu(w, precision, handle=hd)
+    for o in outs:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(outs[0], direct)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_totals_and_pair_count(precision):
+    w = wl.config2(nx=8, ny=8, nz=50)
+    got, st, h = run_gpu(w, precision, nsteps=1)
+    x = wl.bin_masses(w.nbins)
+    mb, ma, nb, na = [t.cpu().numpy() for t in h.totals()]
+    m0 = (w.N[:, 0, :] * x).sum(axis=1)
+    m1 = (got[:, 0, :] * x).sum(axis=1)
+    assert np.allclose(mb, m0, rtol=1e-14, atol=0)
+    assert np.allclose(ma, m1, rtol=1e-14, atol=0)
+    assert np.allclose(nb, w.N.sum(axis=(1, 2)), rtol=1e-14, atol=0)
+    assert np.all(na <= nb * (1 + 1e-12))
+    # pairs of one step: both bins active (M >= theta M_tot), target on grid
+    M = w.N[:, 0, :] * x
+    tot = M.sum(axis=1, keepdims=True)
+    act = (M > 0) & (M >= 1e-30 * tot)
+    n = act.sum(axis=1)
+    top = act[:, -1]
+    want = int((n * (n + 1) // 2 - top).sum())
+    assert st["pair_evals"] == want
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_full_size_thunderstorm_sampled(precision):
+    """The benchmark workload at full size (256 x 256 x 50 points, 100 steps
+    of 2 s) in the benchmark's launch configuration; 256 sampled cloudy
+    points checked against the oracle, conservation and positivity checked
+    on every point through the FP64 totals."""
+    w = wl.config2()
+    L = _lib()
+    h = L.FsbmCoal.from_workload(w, precision=precision)
+    N = torch.from_numpy(w.N).to("cuda")
+    p = torch.from_numpy(w.p).to("cuda")
+    h.step(N, p, w.dt, w.nsteps)
+    torch.cuda.synchronize()
+    mb, ma, nb, na = [t.cpu().numpy() for t in h.totals()]
+    cl = mb > 0
+    assert np.max(np.abs(ma[cl] - mb[cl]) / mb[cl]) <= DRIFT
+    assert np.all(na <= nb * (1 + 1e-12))
+    idx = wl.sample_active(w, 256, seed=7)
+    got = N[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    assert np.all(got >= 0)
+    sub = w.subset(idx)
+    ref, x = run_oracle(sub)
+    check(got, ref, sub.N, x, precision, "full-sampled")
+    st = h.stats()
+    assert st["active_points"] == int(cl.sum())
