@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=50)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (the "
+                         "reference kernel for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -157,6 +160,16 @@ def main():
     from paper_2409_07232_amd import _lib as L
     from paper_2409_07232_amd import workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written":
+                          n * 8, "dispatches": 3}), flush=True)
+        return
     L.load()
     log("generating workload")
     w = wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)
