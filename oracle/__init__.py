@@ -68,7 +68,7 @@ def _load():
         lib.fsbm_oracle_run.argtypes = [ctypes.POINTER(_Desc), dp, dp,
                                         ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_int32, dp, dp, dp, dp, lp,
-                                        ctypes.c_int32]
+                                        ip, ctypes.c_int32]
         lib.fsbm_oracle_run.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
@@ -148,17 +148,20 @@ class OracleModel:
             raise ValueError("p has the wrong length")
         outs = [np.empty(P) for _ in range(4)] if totals else [None] * 4
         lim = ctypes.c_int64(0)
+        lim_pt = np.zeros(P, dtype=np.int32)
         rc = _load().fsbm_oracle_run(
             ctypes.byref(self._desc), _dptr(N), _dptr(p), P, float(dt),
             int(nsteps), *[(_dptr(o) if o is not None else None)
-                           for o in outs], ctypes.byref(lim), int(nthreads))
+                           for o in outs], ctypes.byref(lim),
+            lim_pt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            int(nthreads))
         if rc:
             raise ValueError("oracle rejected its input")
+        res = {"limiter_steps": int(lim.value), "limiter_per_point": lim_pt}
         if totals:
-            return {"mass_before": outs[0], "mass_after": outs[1],
-                    "num_before": outs[2], "num_after": outs[3],
-                    "limiter_steps": int(lim.value)}
-        return {"limiter_steps": int(lim.value)}
+            res.update({"mass_before": outs[0], "mass_after": outs[1],
+                        "num_before": outs[2], "num_after": outs[3]})
+        return res
 
 
 def flux_fraction(c: float, x1: float) -> float:

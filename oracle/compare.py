@@ -18,16 +18,27 @@ def masses(N: np.ndarray, x: np.ndarray) -> np.ndarray:
     return N * x[None, None, :]
 
 
-def rel_bin(N_cand, N_ref, x, floor=1e-9):
+def rel_bin(N_cand, N_ref, x, floor=1e-9, report=False):
+    """floor: scalar or per-point array.  With report=True also returns the
+    worst (point, species, bin) and its masses relative to the point total."""
     Mc = masses(np.asarray(N_cand, dtype=np.float64), x)
     Mr = masses(np.asarray(N_ref, dtype=np.float64), x)
     P = Mr.shape[0]
     tot = Mr.reshape(P, -1).sum(axis=1)
-    den = np.maximum(np.abs(Mr), floor * tot[:, None, None])
+    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
+    den = np.maximum(np.abs(Mr), (fl * tot)[:, None, None])
     err = np.abs(Mc - Mr)
     with np.errstate(invalid="ignore", divide="ignore"):
         r = np.where(den > 0, err / np.where(den > 0, den, 1.0),
                      np.where(err > 0, np.inf, 0.0))
+    if report:
+        if not r.size:
+            return 0.0, None
+        w = np.unravel_index(int(np.argmax(r)), r.shape)
+        t = tot[w[0]] if tot[w[0]] > 0 else 1.0
+        return float(r.max()), {"point": int(w[0]), "species": int(w[1]),
+                                "bin": int(w[2]), "ref_frac": Mr[w] / t,
+                                "cand_frac": Mc[w] / t}
     return float(r.max()) if r.size else 0.0
 
 

@@ -224,10 +224,25 @@ static int pair_contrib(const ctx_t *cx, const double *Mt, const double *N,
     double f = fsbm_oracle_flux_fraction(cx->ct[i * B + j], x1);
     F = f * Sm;
   }
-  add_entry(out, a * B + i, -A);
-  add_entry(out, b * B + j, -Bm);
-  add_entry(out, P * B + k, Sm - F);
-  if (k <= B - 2) add_entry(out, P * B + k + 1, F);
+  /* Contributions to the same bin are combined first [S4].  When the
+     merged mass lands in one of the two source bins, that bin's combined
+     contribution is formed directly as the other source's collided mass
+     minus the flux, not as -Bm + ((A + Bm) - F): the rounding of A + Bm
+     alone is up to u Bm / 2, far above A - F when a large particle
+     collects a small one. */
+  const int qa = a * B + i, qb = b * B + j, qk = P * B + k;
+  if (qk == qb && qk != qa) {
+    add_entry(out, qa, -A);
+    add_entry(out, qb, A - F);
+  } else if (qk == qa && qk != qb) {
+    add_entry(out, qa, Bm - F);
+    add_entry(out, qb, -Bm);
+  } else {
+    add_entry(out, qa, -A);
+    add_entry(out, qb, -Bm);
+    add_entry(out, qk, Sm - F);
+  }
+  if (k <= B - 2) add_entry(out, qk + 1, F);
   return 1;
 }
 
@@ -360,7 +375,8 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t npoints, double dt, int32_t nsteps,
                     double *mass_before, double *mass_after,
                     double *num_before, double *num_after,
-                    int64_t *limiter_steps, int32_t nthreads) {
+                    int64_t *limiter_steps, int32_t *limiter_per_point,
+                    int32_t nthreads) {
   if (check_desc(d) || npoints < 0 || nsteps < 0 || !(dt > 0.0) ||
       !isfinite(dt))
     return -1;
@@ -412,8 +428,11 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
         point_totals(&cx, Np, &m0, &n0);
         if (mass_before) mass_before[pt] = m0;
         if (num_before) num_before[pt] = n0;
+        int32_t lim_pt = 0;
         for (int st = 0; st < nsteps; ++st)
-          lim_total += step_point(&cx, Np, p[pt], dt, &wk);
+          lim_pt += step_point(&cx, Np, p[pt], dt, &wk);
+        lim_total += lim_pt;
+        if (limiter_per_point) limiter_per_point[pt] = lim_pt;
         if (mass_after || num_after) {
           point_totals(&cx, Np, &m0, &n0);
           if (mass_after) mass_after[pt] = m0;

@@ -48,13 +48,15 @@ typedef struct {
 /* Advance npoints independent points by nsteps steps of dt, in place.
  * N: host [npoints][S][B].  p: host [npoints].  Optional outputs (may be
  * NULL): per-point total mass / number before the first and after the last
- * step, and the number of point-steps in which the limiter fired.
+ * step, the number of point-steps in which the limiter fired, and per point
+ * the number of its steps in which it fired.
  * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad input. */
 int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t npoints, double dt, int32_t nsteps,
                     double *mass_before, double *mass_after,
                     double *num_before, double *num_after,
-                    int64_t *limiter_steps, int32_t nthreads);
+                    int64_t *limiter_steps, int32_t *limiter_per_point,
+                    int32_t nthreads);
 
 /* Bin masses x_k, k = 0..B-1. */
 int fsbm_oracle_grid(const fsbm_oracle_desc *d, double *x);
