@@ -14,6 +14,13 @@ steps / time) of the FP32-compensated path; the plain FP64 path is reported
 beside it.  The roofline entry is for the dominant kernel (the collision
 step kernel), timed with HIP events on the stream it runs on.  The CPU
 baseline is the FP64 oracle on a bounded sample of the same workload.
+
+--workload selects the other measured shapes (each prints its own line with
+the same fields; the default run prints the headline line only):
+  four_species     2^20 points, liquid/ice/snow/graupel, 33 bins
+  refined66|132|264  262,144 points, liquid + graupel, refined grids
+  mixed            2^22 points, 10% cloudy, 33/66/132-bin grids in one
+                   persistent launch (FP32C) beside per-grid FP64 launches
 """
 
 import argparse
@@ -42,8 +49,16 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 path beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=1 << 14)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--workload", default="thunderstorm",
+                    choices=["thunderstorm", "four_species", "refined66",
+                             "refined132", "refined264", "mixed"])
+    ap.add_argument("--collision-steps", type=int, default=0,
+                    help="collision steps per call (default: the "
+                         "workload's 100)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target oracle time of the CPU baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps (default: the workload's)")
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--ny", type=int, default=256)
     ap.add_argument("--nz", type=int, default=50)
@@ -57,41 +72,77 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def time_path(w, precision, steps, warmup, N0, p):
-    """Warm up, then time `steps` calls; returns a result dict."""
-    import torch
+def kernel_name(st, precision, nbins):
+    f32 = precision == 1
+    if st["kernel"] == 0:
+        return "lane_step_%s<%d>" % ("f32c" if f32 else "f64", nbins)
+    return "wave_step<%s>" % ("F32" if f32 else "F64")
 
+
+def time_calls(run_once, handles, steps, warmup, nsteps):
+    """Warm up, then time `steps` calls of run_once(); the first handle
+    holds the launch timings and pair counters of a multi-grid call."""
+    import torch
+    for _ in range(warmup):
+        run_once()
+    torch.cuda.synchronize()
+    st0 = [h.stats() for h in handles]
+    pairs = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_once()
+        sts = [h.stats() for h in handles]   # synchronises the stream
+        pairs += sum(st["pair_evals"] for st in sts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = [h.stats() for h in handles]
+    launches = sum(b["kernel_launches"] - a["kernel_launches"]
+                   for a, b in zip(st0, st1))
+    kms = sum(b["kernel_ms"] - a["kernel_ms"] for a, b in zip(st0, st1))
+    active = sum(st["active_points"] for st in st1)
+    secs = t1 - t0
+    return {"secs": secs, "ms_per_step": 1e3 * secs / steps,
+            "updates_per_s": active * nsteps * steps / secs,
+            "active_points": active, "pair_evals": pairs,
+            "kernel_launches": launches, "kernel_ms": kms,
+            "kernel_avg_ms": kms / max(launches, 1),
+            "limiter_steps": sum(st["limiter_steps"] for st in st1),
+            "fallback_steps": sum(st["fp64_fallback_steps"] for st in st1),
+            "stats": st1[0]}
+
+
+def time_path(w, precision, steps, warmup, N0, p):
+    """One handle, one fsbm_coal_step per benchmark step."""
     from paper_2409_07232_amd import _lib as L
     h = L.FsbmCoal.from_workload(w, precision=precision,
                                  flags=L.FLAG_PROFILE)
     N = N0.clone()
-    for _ in range(warmup):
-        h.step(N, p, w.dt, w.nsteps)
-    torch.cuda.synchronize()
-    st0 = h.stats()
-    pairs = 0
-    active = st0["active_points"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        h.step(N, p, w.dt, w.nsteps)
-        st = h.stats()          # synchronises the stream
-        pairs += st["pair_evals"]
-        active = st["active_points"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = h.stats()
-    launches = st1["kernel_launches"] - st0["kernel_launches"]
-    kms = st1["kernel_ms"] - st0["kernel_ms"]
+    r = time_calls(lambda: h.step(N, p, w.dt, w.nsteps), [h], steps, warmup,
+                   w.nsteps)
     h.close()
-    secs = t1 - t0
-    return {"secs": secs, "ms_per_step": 1e3 * secs / steps,
-            "updates_per_s": active * w.nsteps * steps / secs,
-            "active_points": active, "pair_evals": pairs,
-            "kernel_launches": launches, "kernel_ms": kms,
-            "kernel_avg_ms": kms / max(launches, 1),
-            "limiter_steps": st1["limiter_steps"],
-            "fallback_steps": st1["fp64_fallback_steps"]}
+    return r
+
+
+def time_multi(ws, precision, steps, warmup, N0s, ps, batched):
+    """Several grids: one fsbm_coal_step_multi call (batched) or one
+    fsbm_coal_step call per grid."""
+    from paper_2409_07232_amd import _lib as L
+    hs = [L.FsbmCoal.from_workload(w, precision=precision,
+                                   flags=L.FLAG_PROFILE) for w in ws]
+    Ns = [n.clone() for n in N0s]
+    if batched:
+        # the widest grid first, as the library expects its scratch to fit
+        def run_once():
+            L.step_multi(hs, Ns, ps, ws[0].dt, ws[0].nsteps)
+    else:
+        def run_once():
+            for h, N, p, w in zip(hs, Ns, ps, ws):
+                h.step(N, p, w.dt, w.nsteps)
+    r = time_calls(run_once, hs, steps, warmup, ws[0].nsteps)
+    for h in hs:
+        h.close()
+    return r
 
 
 def roofline(res, peak):
@@ -102,49 +153,113 @@ def roofline(res, peak):
             "traffic": None}
 
 
-def cpu_baseline(w, npts, nsteps):
+def _oracle_model(w):
+    import oracle
+    return oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
+                              w.product, x1_g=w.x1_g, s=w.s, theta=w.theta)
+
+
+def cpu_baseline(ws, seconds, nsteps):
+    """The oracle on a seeded sample of cloudy points of each grid (sample
+    sizes proportional to the grids' cloudy counts), grown until one run
+    takes about `seconds`; the reported rate is that run's."""
     import numpy as np
 
     import oracle
     from paper_2409_07232_amd import workloads as wl
-    idx = wl.sample_active(w, npts, seed=11)
-    sub = w.subset(idx)
-    om = oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
-                            w.product, x1_g=w.x1_g, s=w.s, theta=w.theta)
-    N = np.array(sub.N, copy=True)
     cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    om.run(N, sub.p, w.dt, nsteps, nthreads=cores)
-    secs = time.perf_counter() - t0
-    return {"value": round(len(idx) * nsteps / secs, 1),
+    ncloudy = [int(w.cloudy().sum()) for w in ws]
+    share = [n / max(sum(ncloudy), 1) for n in ncloudy]
+    # run full-length samples, rescaling the point count from each run's
+    # time, until one takes at least a third of the target (or covers every
+    # cloudy point); the last run is the one reported
+    base = 16 * cores
+    while True:
+        npts = [min(nc, max(1, int(round(base * sh))))
+                for sh, nc in zip(share, ncloudy)]
+        samples = []
+        t0 = time.perf_counter()
+        for w, n in zip(ws, npts):
+            idx = wl.sample_active(w, n, seed=11)
+            sub = w.subset(idx)
+            N = np.array(sub.N, copy=True)
+            res = _oracle_model(w).run(N, sub.p, w.dt, nsteps,
+                                       nthreads=cores)
+            samples.append((idx, N, res["limiter_per_point"]))
+        secs = time.perf_counter() - t0
+        if secs >= seconds / 3 or all(n >= nc for n, nc in
+                                      zip(npts, ncloudy)):
+            break
+        base = int(base * min(16.0, seconds / max(secs, 1e-3)))
+    tot = sum(len(s[0]) for s in samples)
+    desc = " + ".join("%d of %s" % (len(s[0]), w.name)
+                      for s, w in zip(samples, ws))
+    return {"value": round(tot * nsteps / secs, 1),
             "unit": "grid-point collision updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": "%d seeded cloudy points x %d steps of %.0f s of the "
-                      "same workload, FP64, %.1f s" % (len(idx), nsteps,
-                                                       w.dt, secs)}, idx, N
+            "sample": "%s seeded cloudy points x %d steps of %.0f s of the "
+                      "same workload, FP64, %.1f s" % (desc, nsteps, ws[0].dt,
+                                                       secs)}, samples
 
 
-def parity(w, idx, Nref, nsteps):
-    """GPU result on the CPU-baseline sample against the oracle's."""
+def parity(ws, samples, nsteps):
+    """GPU results on the CPU-baseline sample against the oracle's (R15
+    rel_bin; points the oracle limited judged with the 1e-3 floor)."""
     import numpy as np
     import torch
 
     from oracle import compare
     from paper_2409_07232_amd import _lib as L
     from paper_2409_07232_amd import workloads as wl
-    sub = w.subset(idx)
-    x = wl.bin_masses(w.nbins, w.s, w.x1_g)
     out = {}
     for name, prec in (("fp32c", L.FSBM_FP32C), ("fp64", L.FSBM_FP64)):
-        h = L.FsbmCoal.from_workload(w, precision=prec)
-        N = torch.from_numpy(np.array(sub.N, copy=True)).to("cuda")
-        p = torch.from_numpy(np.array(sub.p, copy=True)).to("cuda")
-        h.step(N, p, w.dt, nsteps)
-        got = N.cpu().numpy()
-        h.close()
-        out[name] = {"rel_bin": float("%.3e" % compare.rel_bin(got, Nref, x)),
-                     "drift": float("%.3e" % compare.drift(got, sub.N, x))}
+        err = drift = 0.0
+        for w, (idx, Nref, lim) in zip(ws, samples):
+            sub = w.subset(idx)
+            x = wl.bin_masses(w.nbins, w.s, w.x1_g)
+            h = L.FsbmCoal.from_workload(w, precision=prec)
+            N = torch.from_numpy(np.array(sub.N, copy=True)).to("cuda")
+            p = torch.from_numpy(np.array(sub.p, copy=True)).to("cuda")
+            h.step(N, p, w.dt, nsteps)
+            got = N.cpu().numpy()
+            h.close()
+            floor = np.where(lim > 0, 1e-3, 1e-9)
+            err = max(err, compare.rel_bin(got, Nref, x, floor=floor))
+            drift = max(drift, compare.drift(got, sub.N, x))
+        out[name] = {"rel_bin": float("%.3e" % err),
+                     "drift": float("%.3e" % drift),
+                     "limited_points": int(sum((s[2] > 0).sum()
+                                               for s in samples))}
     return out
+
+
+def make_workloads(args):
+    """(workloads, config entry) of the selected benchmark workload."""
+    from paper_2409_07232_amd import workloads as wl
+    name = args.workload
+    if name == "thunderstorm":
+        ws = [wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)]
+        cfg = {"workload": "thunderstorm_patch_%dx%dx%d_33bins_liquid" % (
+                   args.nx, args.ny, args.nz),
+               "kernel_tables": "gravitational, 3 pressure levels"}
+    elif name == "four_species":
+        ws = [wl.config3()]
+        cfg = {"workload": "four_species_2^20pts_33bins",
+               "kernel_tables": "10 gravitational pair tables, 3 levels"}
+    elif name.startswith("refined"):
+        nb = int(name[len("refined"):])
+        ws = [wl.config4(nbins=nb)]
+        cfg = {"workload": "liquid_graupel_262144pts_%dbins" % nb,
+               "kernel_tables": "3 gravitational pair tables, 3 levels"}
+    else:
+        ws = wl.config5()
+        ws.sort(key=lambda w: -w.nspecies * w.nbins)
+        cfg = {"workload": "mixed_grids_2^22pts_10pct_cloudy_33_66_132bins",
+               "kernel_tables": "per grid, 3 levels"}
+    if args.collision_steps:
+        for w in ws:
+            w.nsteps = args.collision_steps
+    return ws, cfg
 
 
 def main():
@@ -158,7 +273,6 @@ def main():
     import torch
 
     from paper_2409_07232_amd import _lib as L
-    from paper_2409_07232_amd import workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 8
@@ -171,28 +285,53 @@ def main():
                           n * 8, "dispatches": 3}), flush=True)
         return
     L.load()
-    log("generating workload")
-    w = wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)
-    N0 = torch.from_numpy(w.N).to("cuda")
-    p = torch.from_numpy(w.p).to("cuda")
+    log("generating workload %s" % args.workload)
+    ws, cfg = make_workloads(args)
+    N0s = [torch.from_numpy(w.N).to("cuda") for w in ws]
+    ps = [torch.from_numpy(w.p).to("cuda") for w in ws]
+    multi = len(ws) > 1
     log("timing fp32c: %d warmup + %d steps" % (args.warmup, args.steps))
-    r32 = time_path(w, L.FSBM_FP32C, args.steps, args.warmup, N0, p)
+    if multi:
+        r32 = time_multi(ws, L.FSBM_FP32C, args.steps, args.warmup, N0s, ps,
+                         batched=True)
+    else:
+        r32 = time_path(ws[0], L.FSBM_FP32C, args.steps, args.warmup, N0s[0],
+                        ps[0])
     log("fp32c %.2f ms/step, %.3e updates/s" % (r32["ms_per_step"],
                                                r32["updates_per_s"]))
     r64 = None
     if not args.no_fp64:
-        log("timing fp64")
-        r64 = time_path(w, L.FSBM_FP64, args.steps, args.warmup, N0, p)
+        log("timing fp64" + (" (per-grid launches)" if multi else ""))
+        if multi:
+            r64 = time_multi(ws, L.FSBM_FP64, args.steps, args.warmup, N0s,
+                             ps, batched=False)
+        else:
+            r64 = time_path(ws[0], L.FSBM_FP64, args.steps, args.warmup,
+                            N0s[0], ps[0])
         log("fp64 %.2f ms/step, %.3e updates/s" % (r64["ms_per_step"],
                                                   r64["updates_per_s"]))
-    del N0
-    cpu = None
-    par = None
+    del N0s
+    nsteps = ws[0].nsteps
+    cpu = par = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) on %d points" % args.cpu_points)
-        cpu, idx, Nref = cpu_baseline(w, args.cpu_points, args.cpu_steps)
-        log("cpu %.3e updates/s on %d cores" % (cpu["value"], cpu["cores"]))
-        par = parity(w, idx, Nref, args.cpu_steps)
+        csteps = args.cpu_steps or nsteps
+        log("cpu baseline (oracle), about %.0f s" % args.cpu_seconds)
+        cpu, samples = cpu_baseline(ws, args.cpu_seconds, csteps)
+        log("cpu %.3e updates/s on %d cores (%s)" % (cpu["value"],
+                                                    cpu["cores"],
+                                                    cpu["sample"]))
+        par = parity(ws, samples, csteps)
+    w0 = ws[0]
+    cfg.update({"points": sum(w.npoints for w in ws),
+                "cloudy_points": r32["active_points"],
+                "bins": [w.nbins for w in ws] if multi else w0.nbins,
+                "species": [w.nspecies for w in ws] if multi else
+                w0.nspecies,
+                "dt_s": w0.dt, "collision_steps_per_step": nsteps,
+                "parallelism": "single GPU"})
+    if multi:
+        cfg["launch"] = ("fp32c: one persistent launch over all grids per "
+                         "fused-step group; fp64: one call per grid")
     line = {
         "metric": "grid-point collision updates/s at 33 bins; FP32-comp vs "
                   "FP64, rel err <=1e-5",
@@ -202,25 +341,25 @@ def main():
         "ms_per_step": round(r32["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "thunderstorm_patch_%dx%dx%d_33bins_liquid" % (
-                       args.nx, args.ny, args.nz),
-                   "points": w.npoints, "cloudy_points": r32["active_points"],
-                   "bins": w.nbins, "species": w.nspecies, "dt_s": w.dt,
-                   "collision_steps_per_step": w.nsteps,
-                   "kernel_tables": "gravitational, 3 pressure levels",
-                   "parallelism": "single GPU"},
+        "config": cfg,
         "roofline": roofline(r32, PEAK_FP32_TFLOPS),
-        "kernel": {"name": "lane_step_f32c<33>",
+        "kernel": {"name": kernel_name(r32["stats"], 1, w0.nbins),
                    "avg_launch_ms": round(r32["kernel_avg_ms"], 4),
                    "launches": r32["kernel_launches"],
                    "pair_evals": r32["pair_evals"],
+                   "pairs_per_point_step": round(
+                       r32["pair_evals"] / max(1, r32["active_points"] *
+                                               nsteps * args.steps), 1),
                    "flops_per_pair": FLOPS_PER_PAIR,
+                   "steps_per_launch": r32["stats"]["steps_per_launch"],
+                   "limiter_steps": r32["limiter_steps"],
                    "fallback_steps": r32["fallback_steps"]},
     }
     if r64 is not None:
         line["fp64"] = {"value": round(r64["updates_per_s"], 1),
                         "ms_per_step": round(r64["ms_per_step"], 4),
                         "dtype": "f64",
+                        "kernel": kernel_name(r64["stats"], 0, w0.nbins),
                         "roofline": roofline(r64, PEAK_FP64_TFLOPS),
                         "avg_launch_ms": round(r64["kernel_avg_ms"], 4)}
     if cpu is not None:

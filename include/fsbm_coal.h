@@ -112,7 +112,12 @@ int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
  * 33/66/132-bin batches): the cloudy points of every grid are compacted into
  * one work list and advanced by one persistent kernel per group of fused
  * steps.  Arrays are indexed by grid; same ownership rules as
- * fsbm_coal_step.  All handles must use the same precision.
+ * fsbm_coal_step.  All handles must use the same precision and device, be
+ * distinct, and have S*B <= 768; at most 4 grids.  Results equal those of
+ * fsbm_coal_step per grid with the one-point-per-wave kernel, bit for bit.
+ * The pair, limiter and exact-path counters and the profiled launch
+ * timings of the call are kept in the handle with the largest S*B (the
+ * first one listed if several tie); active_points stays per handle.
  */
 int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
                          double *const *N, const double *const *p_hpa,
@@ -143,7 +148,10 @@ typedef struct {
                              mass inside the grid), summed over points and
                              steps of the last call */
   int64_t limiter_steps;  /* point-steps where the positivity limiter ran */
-  int64_t fp64_fallback_steps; /* FP32C point-steps redone in FP64 */
+  int64_t fp64_fallback_steps; /* point-steps taken on the exact FP64 path:
+                                  once a point's fast kernel finds that the
+                                  limiter may fire, the point takes every
+                                  remaining step of the call there */
   int32_t kernel;         /* 0 = one point per lane, 1 = one point per wave */
   int32_t steps_per_launch;
   int32_t waves_per_block;

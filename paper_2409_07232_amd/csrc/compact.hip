@@ -13,6 +13,12 @@
 //   gather  cloudy point -> slot (stable: point order within a bracket),
 //           bins copied into the structure-of-arrays workspace,
 //           interpolation weight and FP64 totals recorded
+//   sort    (one-point-per-lane kernels only) within chunks of 2048 slots,
+//           points ordered by bracket, top active bin and total mass, then
+//           the state is loaded in that order: a wave of the lane kernels
+//           visits the union of its 64 points' active bins, and points with
+//           similar top bins and similar mass (which sets how fast the top
+//           bin grows) keep that union close to each point's own range
 //   scatter workspace -> caller's [point][species][bin] array, totals
 // Everything stays on the device, so the sequence can be captured in a
 // hipGraph without host round trips.
@@ -122,7 +128,8 @@ __global__ void __launch_bounds__(kCompactThreads)
                    const CompactMeta *__restrict__ meta,
                    int *__restrict__ slot_point, double *__restrict__ state,
                    double *__restrict__ wgt, int slot_cap,
-                   const double *__restrict__ x, double *__restrict__ tot) {
+                   const double *__restrict__ x, double *__restrict__ tot,
+                   int aos, unsigned *__restrict__ keys, double theta) {
   constexpr int kWaves = kCompactThreads / kWave;
   __shared__ int wave_cnt[kWaves][kMaxBuckets];
   const int SB = S * B;
@@ -152,7 +159,24 @@ __global__ void __launch_bounds__(kCompactThreads)
                      before + rank;
     slot_point[slot] = (int)pt;
     wgt[slot] = w;
-    for (int q = 0; q < SB; ++q) state[state_index(q, slot, SB)] = row[q];
+    if (keys) {
+      // sort key: bracket, top active bin, top 16 bits of the total mass
+      // (positive doubles order like their bit patterns); the state is
+      // loaded after the sort
+      double mt = 0.0;
+      for (int q = 0; q < SB; ++q) mt += row[q] * x[q % B];
+      int top = 0;
+      for (int q = 0; q < SB; ++q)
+        if (row[q] * x[q % B] >= theta * mt && row[q] > 0.0) top = q % B;
+      const unsigned long long bits =
+          (unsigned long long)__double_as_longlong(mt);
+      keys[slot] = ((unsigned)l << 24) | ((unsigned)min(top, 255) << 16) |
+                   (unsigned)((bits >> 48) & 0xffffu);
+    } else if (aos) {
+      for (int q = 0; q < SB; ++q) state[state_index_aos(q, slot, SB)] = row[q];
+    } else {
+      for (int q = 0; q < SB; ++q) state[state_index(q, slot, SB)] = row[q];
+    }
   }
   if (inside && tot) {
     double m = 0.0, n = 0.0;
@@ -168,14 +192,85 @@ __global__ void __launch_bounds__(kCompactThreads)
   }
 }
 
-// Padding slots of each bracket (up to the next whole wave) hold no point.
+// Padding slots of each bracket (up to the next whole wave) hold no point;
+// their sort key is the largest of their bracket, so a chunk sort keeps
+// every bracket (with its padding) on the slots it had.
 __global__ void fill_padding(const CompactMeta *__restrict__ meta,
-                             int *__restrict__ slot_point) {
+                             int *__restrict__ slot_point,
+                             unsigned *__restrict__ keys) {
   const int bk = blockIdx.x;
   const int first = meta->bucket_base[bk] + meta->bucket_count[bk];
   const int end = meta->bucket_base[bk + 1];
   const int s = first + threadIdx.x;
-  if (s < end) slot_point[s] = -1;
+  if (s < end) {
+    slot_point[s] = -1;
+    if (keys) keys[s] = ((unsigned)bk << 24) | 0xffffffu;
+  }
+}
+
+constexpr int kSortChunk = 2048;
+constexpr int kSortThreads = 1024;
+
+// Bitonic sort of one chunk of slots by key, with the point index and the
+// interpolation weight carried along (deterministic: ties resolve the same
+// way on every run).
+__global__ void __launch_bounds__(kSortThreads)
+    compact_sort(const CompactMeta *__restrict__ meta,
+                 const unsigned *__restrict__ keys,
+                 int *__restrict__ slot_point, double *__restrict__ wgt) {
+  __shared__ unsigned ks[kSortChunk];
+  __shared__ int ps[kSortChunk];
+  __shared__ double ws[kSortChunk];
+  const int nslots = meta->nslots;
+  const int c0 = blockIdx.x * kSortChunk;
+  if (c0 >= nslots) return;
+  const int cnt = min(kSortChunk, nslots - c0);
+  for (int t = threadIdx.x; t < kSortChunk; t += kSortThreads) {
+    const bool in = t < cnt;
+    ks[t] = in ? keys[c0 + t] : 0xffffffffu;
+    ps[t] = in ? slot_point[c0 + t] : -1;
+    ws[t] = in ? wgt[c0 + t] : 0.0;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kSortChunk; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < kSortChunk / 2; t += kSortThreads) {
+        const int a = 2 * t - (t & (stride - 1));
+        const int b = a + stride;
+        const bool up = (a & size) == 0;
+        const unsigned ka = ks[a], kb = ks[b];
+        if ((ka > kb) == up && ka != kb) {
+          ks[a] = kb;
+          ks[b] = ka;
+          const int pa = ps[a];
+          ps[a] = ps[b];
+          ps[b] = pa;
+          const double wa = ws[a];
+          ws[a] = ws[b];
+          ws[b] = wa;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < cnt; t += kSortThreads) {
+    slot_point[c0 + t] = ps[t];
+    wgt[c0 + t] = ws[t];
+  }
+}
+
+// State of every compacted point into its (sorted) slot, tiled layout.
+__global__ void __launch_bounds__(kCompactThreads)
+    compact_load(const double *__restrict__ N,
+                 const CompactMeta *__restrict__ meta,
+                 const int *__restrict__ slot_point, int SB,
+                 double *__restrict__ state) {
+  const int slot = blockIdx.x * kCompactThreads + threadIdx.x;
+  if (slot >= meta->nslots) return;
+  const int pt = slot_point[slot];
+  if (pt < 0) return;
+  const double *row = N + (int64_t)pt * SB;
+  for (int q = 0; q < SB; ++q) state[state_index(q, slot, SB)] = row[q];
 }
 
 __global__ void __launch_bounds__(kCompactThreads)
@@ -184,7 +279,7 @@ __global__ void __launch_bounds__(kCompactThreads)
                  const int *__restrict__ slot_point,
                  const double *__restrict__ state, int slot_cap,
                  const double *__restrict__ x, double *__restrict__ tot,
-                 int64_t npoints) {
+                 int64_t npoints, int aos) {
   const int slot = blockIdx.x * kCompactThreads + threadIdx.x;
   if (slot >= meta->nslots) return;
   const int pt = slot_point[slot];
@@ -193,7 +288,8 @@ __global__ void __launch_bounds__(kCompactThreads)
   double *row = N + (int64_t)pt * SB;
   double m = 0.0, n = 0.0;
   for (int q = 0; q < SB; ++q) {
-    const double v = state[state_index(q, slot, SB)];
+    const double v = aos ? state[state_index_aos(q, slot, SB)]
+                         : state[state_index(q, slot, SB)];
     row[q] = v;
     m += v * x[q % B];
     n += v;
@@ -244,29 +340,48 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  const CompactMeta *meta, int nblocks,
                                  int *slot_point, double *state, double *wgt,
                                  int slot_cap, const double *x, double *tot,
+                                 int aos, unsigned *keys, double theta,
                                  hipStream_t st) {
   hipLaunchKernelGGL(compact_gather, dim3(nblocks), dim3(kCompactThreads), 0,
                      st, N, p, npoints, S, B, plev, L, block_offsets, meta,
-                     slot_point, state, wgt, slot_cap, x, tot);
+                     slot_point, state, wgt, slot_cap, x, tot, aos, keys,
+                     theta);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
-                               int slot_cap, hipStream_t st) {
+                               unsigned *keys, int slot_cap, hipStream_t st) {
   (void)slot_cap;
   hipLaunchKernelGGL(fill_padding, dim3(kMaxBuckets), dim3(kWave), 0, st,
-                     meta, slot_point);
+                     meta, slot_point, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_sort_load(const double *N, const CompactMeta *meta,
+                                    const unsigned *keys, int *slot_point,
+                                    double *wgt, int SB, double *state,
+                                    int slot_cap, hipStream_t st) {
+  // every slot below slot_cap belongs to some chunk; chunks past the
+  // compacted count return at once
+  const int chunks = (slot_cap + kSortChunk - 1) / kSortChunk;
+  hipLaunchKernelGGL(compact_sort, dim3(chunks), dim3(kSortThreads), 0, st,
+                     meta, keys, slot_point, wgt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;
+  hipLaunchKernelGGL(compact_load, dim3(blocks), dim3(kCompactThreads), 0, st,
+                     N, meta, slot_point, SB, state);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
                           const CompactMeta *meta, const int *slot_point,
                           const double *state, int slot_cap, const double *x,
-                          double *tot, hipStream_t st) {
+                          double *tot, int aos, hipStream_t st) {
   const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;
   hipLaunchKernelGGL(scatter_back, dim3(blocks), dim3(kCompactThreads), 0, st,
                      N, S, B, meta, slot_point, state, slot_cap, x, tot,
-                     npoints);
+                     npoints, aos);
   return hipGetLastError();
 }
 

@@ -109,6 +109,20 @@ __device__ __forceinline__ void comp_add(float &s, float &c, float x) {
   s = t;
 }
 
+// The same for a non-negative running sum and a non-negative term: with
+// the larger operand first, Dekker's Fast2Sum recovers the same exact
+// rounding error as TwoSum (identical s and c) in one operation less.
+__device__ __forceinline__ void comp_add_pos(float &s, float &c, float x) {
+  // max and min as three-operand medians (no NaN canonicalisation needed:
+  // both operands are finite)
+  const float a = __builtin_amdgcn_fmed3f(s, x, __builtin_inff());
+  const float b = __builtin_amdgcn_fmed3f(s, x, -__builtin_inff());
+  const float t = a + b;
+  const float e = b - (t - a);
+  c += e;
+  s = t;
+}
+
 // ------------------------------------------------------- flux fraction
 // f(c, x1) = integral over [1/2 - c, 1/2] of exp(x1 t) dt, clamped to
 // [0, 1]: the fraction of the merged mass that an exponential sub-bin
@@ -152,6 +166,5 @@ __device__ __forceinline__ float flux_fraction_f32(float c, float cl2,
 // clamp of f decides) while 2^(lam/2) stays finite.
 constexpr float kLamFloor = (float)(kX1Floor / 0.69314718055994530942);
 constexpr float kLamCeil = (float)(173.0 / 0.69314718055994530942);
-constexpr float kLn2f = 0.69314718055994530942f;
 
 }  // namespace fsbm

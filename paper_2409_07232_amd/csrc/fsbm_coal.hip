@@ -1,16 +1,22 @@
 // fsbm_coal.hip -- host side of the C ABI (include/fsbm_coal.h): handle,
-// model tables, workspace, launch sequence, hipGraph cache, diagnostics.
+// model tables, workspace, launch sequence, hipGraph cache, autotuning,
+// diagnostics.
 //
-// A call of fsbm_coal_step enqueues, on the caller's stream:
-//   zero counters -> compaction (count, scan, gather, padding) ->
-//   ceil(nsteps / steps_per_launch) step kernels -> scatter back.
-// With a non-null stream the sequence is captured once into a hipGraph and
-// replayed while (N, p, npoints, dt, nsteps, stream, launch shape) repeat.
+// A step call enqueues, on the caller's stream:
+//   per grid: zero counters -> compaction (count, scan, gather, padding)
+//   ceil(nsteps / steps_per_launch) x (collision kernel, exact-path kernel)
+//   per grid: scatter back
+// One species on the mass-doubling grid with at most kLaneMaxBins bins runs
+// the one-point-per-lane kernels; everything else (and every multi-grid
+// call) runs the one-point-per-wave kernel.  With a non-null stream the
+// sequence is captured once into a hipGraph and replayed while the call's
+// arguments and launch shape repeat.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -24,19 +30,22 @@ namespace {
 constexpr int kCompactBlock = 256;
 constexpr double kDefaultX1 = 3.3510321638291124e-11;  // 2 um water drop
 constexpr double kHitTol = 1e-12;
+constexpr int kDefaultSteps = 10;
+constexpr int kDefaultWaveBlocks = 2048;
 
+// Arguments a captured graph depends on.
 struct GraphKey {
-  const void *N = nullptr;
-  const void *p = nullptr;
-  int64_t npoints = -1;
+  std::vector<const void *> ptrs;  // N and p of every grid
+  std::vector<int64_t> npts;
+  std::vector<const void *> handles;
   double dt = 0.0;
   int nsteps = -1;
   void *stream = nullptr;
-  int spl = 0, wpb = 0;
+  int spl = 0, wpb = 0, blocks = 0;
   bool operator==(const GraphKey &o) const {
-    return N == o.N && p == o.p && npoints == o.npoints && dt == o.dt &&
-           nsteps == o.nsteps && stream == o.stream && spl == o.spl &&
-           wpb == o.wpb;
+    return ptrs == o.ptrs && npts == o.npts && handles == o.handles &&
+           dt == o.dt && nsteps == o.nsteps && stream == o.stream &&
+           spl == o.spl && wpb == o.wpb && blocks == o.blocks;
   }
 };
 
@@ -45,7 +54,8 @@ struct GraphKey {
 struct fsbm_coal_s {
   int device = 0;
   int B = 0, S = 0, L = 0, s = 1, precision = FSBM_FP64, flags = 0;
-  int steps_per_launch = 0, waves_per_block = 0;
+  int steps_per_launch = 0, waves_per_block = 0, wave_blocks = 0;
+  bool lane = false;  // one-point-per-lane kernels apply
   double x1 = kDefaultX1, theta = 1e-30;
   std::vector<double> x, ct;
   std::vector<int> kt, product;
@@ -54,9 +64,9 @@ struct fsbm_coal_s {
   DevModel dm{};
   // workspace
   void *wmem = nullptr;
-  size_t wbytes = 0;
   int64_t wpoints = -1;  // points the workspace was laid out for
   DevWork ws{};
+  double *scratch = nullptr;  // exact path of the wave kernel
   int nblocks = 0;
   // graph cache
   hipGraph_t graph = nullptr;
@@ -76,9 +86,7 @@ struct fsbm_coal_s {
 namespace {
 
 int hip_fail(fsbm_coal_t h, hipError_t e, const char *what) {
-  if (h) {
-    h->last_error = std::string(what) + ": " + hipGetErrorString(e);
-  }
+  if (h) h->last_error = std::string(what) + ": " + hipGetErrorString(e);
   return FSBM_EHIP;
 }
 
@@ -88,28 +96,115 @@ int hip_fail(fsbm_coal_t h, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
   } while (0)
 
+#define RC_TRY(call)                 \
+  do {                               \
+    const int rc_ = (call);          \
+    if (rc_ != FSBM_OK) return rc_; \
+  } while (0)
+
 double grid_mass(double x1, int s, int k) {
   return ldexp(x1 * pow(2.0, (double)(k % s) / (double)s), k / s);
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Tunable launch shape: the cache file holds lines
-// "B S precision steps_per_launch waves_per_block".
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// Launch-shape cache: lines "B S precision kernel steps_per_launch
+// waves_per_block wave_blocks".
 void read_tune_cache(fsbm_coal_t h) {
   const char *path = getenv("FSBM_TUNE_CACHE");
   if (!path) return;
   FILE *f = fopen(path, "r");
   if (!f) return;
-  int B, S, pr, spl, wpb;
-  while (fscanf(f, "%d %d %d %d %d", &B, &S, &pr, &spl, &wpb) == 5) {
-    if (B == h->B && S == h->S && pr == h->precision && spl > 0 &&
-        wpb >= 1 && wpb <= 4) {
+  int B, S, pr, kern, spl, wpb, wb;
+  while (fscanf(f, "%d %d %d %d %d %d %d", &B, &S, &pr, &kern, &spl, &wpb,
+                &wb) == 7) {
+    if (B == h->B && S == h->S && pr == h->precision &&
+        kern == (h->lane ? 0 : 1) && spl > 0 && wpb >= 1 && wpb <= 2 &&
+        wb >= 0) {
       if (h->steps_per_launch == 0) h->steps_per_launch = spl;
       h->waves_per_block = wpb;
+      h->wave_blocks = wb;
     }
   }
   fclose(f);
+}
+
+void write_tune_cache(fsbm_coal_t h) {
+  const char *path = getenv("FSBM_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%d %d %d %d %d %d %d\n", h->B, h->S, h->precision,
+          h->lane ? 0 : 1, h->steps_per_launch, h->waves_per_block,
+          h->wave_blocks);
+  fclose(f);
+}
+
+// Pair lists of the one-point-per-wave kernel: for every bin the pairs whose
+// merged mass lands in it (canonical order), for every bin the pairs it
+// loses mass in (transfers that stay in the bin are left out), and a
+// load-balanced assignment of bins to the 64 lanes.
+int build_wave_tables(fsbm_coal_t h, std::vector<short> &own,
+                      std::vector<int> &tgt_off, std::vector<unsigned> &tgt,
+                      std::vector<int> &loss_off,
+                      std::vector<unsigned> &loss) {
+  const int B = h->B, S = h->S, SB = S * B;
+  std::vector<std::vector<unsigned>> T(SB), Lq(SB);
+  for (int a = 0; a < S; ++a)
+    for (int b = a; b < S; ++b)
+      for (int i = 0; i < B; ++i)
+        for (int j = (a == b ? i : 0); j < B; ++j) {
+          const int k = h->kt[(size_t)i * B + j];
+          if (k < 0) continue;
+          const int P = h->product[(size_t)a * S + b];
+          const int qt = P * B + k, qa = a * B + i, qb = b * B + j;
+          const unsigned e = pack_pair(a, i, b, j);
+          const unsigned et =
+              e | (qa == qt ? kEntTA : 0u) | (qb == qt ? kEntTB : 0u);
+          T[qt].push_back(et);
+          if (qa == qb) {
+            Lq[qa].push_back(e | kEntSelf);
+          } else {
+            if (qa != qt) Lq[qa].push_back(e);
+            if (qb != qt) Lq[qb].push_back(e | kEntSideB);
+          }
+        }
+  tgt_off.assign(SB + 1, 0);
+  loss_off.assign(SB + 1, 0);
+  tgt.clear();
+  loss.clear();
+  for (int q = 0; q < SB; ++q) {
+    tgt_off[q] = (int)tgt.size();
+    tgt.insert(tgt.end(), T[q].begin(), T[q].end());
+    loss_off[q] = (int)loss.size();
+    loss.insert(loss.end(), Lq[q].begin(), Lq[q].end());
+  }
+  tgt_off[SB] = (int)tgt.size();
+  loss_off[SB] = (int)loss.size();
+  // longest-processing-time assignment; a target entry costs about four
+  // loss entries
+  if (SB > kWave * kMaxOwn) return FSBM_EUNSUPPORTED;
+  std::vector<int> order(SB);
+  std::vector<double> wgt(SB);
+  for (int q = 0; q < SB; ++q) {
+    order[q] = q;
+    wgt[q] = 4.0 * T[q].size() + Lq[q].size() + 1.0;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return wgt[a] > wgt[b]; });
+  std::vector<double> load(kWave, 0.0);
+  std::vector<int> cnt(kWave, 0);
+  own.assign((size_t)kWave * kMaxOwn, (short)-1);
+  for (int q : order) {
+    int best = -1;
+    for (int l = 0; l < kWave; ++l)
+      if (cnt[l] < kMaxOwn && (best < 0 || load[l] < load[best])) best = l;
+    own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
+    load[best] += wgt[q];
+  }
+  return FSBM_OK;
 }
 
 int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
@@ -135,14 +230,14 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       h->kt[(size_t)i * B + j] = k;
       h->ct[(size_t)i * B + j] = c;
     }
-  // device image: x, invx, ct, Kd (FP64, 8-byte aligned first), then FP32
-  // and int arrays
+  // per bracket (K_{l+1}, K_l - K_{l+1}) in FP64 and FP32
   const size_t nKd = (size_t)npairs * nbr * B * B * 2;
   std::vector<double> invx(B), Kd(nKd);
-  std::vector<float> invxf(B), ctf((size_t)B * B), Kf(nKd);
+  std::vector<float> invxf(B), xf(B), ctf((size_t)B * B), Kf(nKd);
   for (int k = 0; k < B; ++k) {
     invx[k] = 1.0 / h->x[k];
     invxf[k] = (float)invx[k];
+    xf[k] = (float)h->x[k];
   }
   for (size_t q = 0; q < (size_t)B * B; ++q) ctf[q] = (float)h->ct[q];
   for (int ab = 0; ab < npairs; ++ab)
@@ -165,11 +260,10 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
         Kf[o] = (float)lo;
         Kf[o + 1] = (float)d;
       }
-  // species pair 0 tables transposed to [br][j][i] for the one-point-per-
-  // lane kernels
+  // species pair 0 transposed to [br][j][i] for the lane kernels
   const size_t nT = (size_t)nbr * B * B * 2;
   std::vector<double> KdT(nT), ctT((size_t)B * B);
-  std::vector<float> KfT(nT), ctfT((size_t)B * B);
+  std::vector<float> KfT(nT), ctfT((size_t)B * B * 2);
   for (int br = 0; br < nbr; ++br)
     for (int i = 0; i < B; ++i)
       for (int j = 0; j < B; ++j)
@@ -182,8 +276,18 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   for (int i = 0; i < B; ++i)
     for (int j = 0; j < B; ++j) {
       ctT[(size_t)j * B + i] = h->ct[(size_t)i * B + j];
-      ctfT[(size_t)j * B + i] = ctf[(size_t)i * B + j];
+      // FP32 Courant number and its product with ln 2, rounded as the
+      // kernels would round it
+      const float cf = ctf[(size_t)i * B + j];
+      ctfT[((size_t)j * B + i) * 2] = cf;
+      ctfT[((size_t)j * B + i) * 2 + 1] = cf * kLn2f;
     }
+  std::vector<short> own;
+  std::vector<int> tgt_off, loss_off;
+  std::vector<unsigned> tgt, loss;
+  const bool wave_ok = S * B <= kWave * kMaxOwn;
+  if (wave_ok) RC_TRY(build_wave_tables(h, own, tgt_off, tgt, loss_off, loss));
+  if (!h->lane && !wave_ok) return FSBM_EUNSUPPORTED;
   struct Part {
     const void *src;
     size_t bytes;
@@ -203,7 +307,13 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       {KdT.data(), sizeof(double) * nT, 0},
       {ctT.data(), sizeof(double) * B * B, 0},
       {KfT.data(), sizeof(float) * nT, 0},
-      {ctfT.data(), sizeof(float) * B * B, 0},
+      {ctfT.data(), sizeof(float) * B * B * 2, 0},
+      {xf.data(), sizeof(float) * B, 0},
+      {own.data(), sizeof(short) * own.size(), 0},
+      {tgt_off.data(), sizeof(int) * tgt_off.size(), 0},
+      {tgt.data(), sizeof(unsigned) * tgt.size(), 0},
+      {loss_off.data(), sizeof(int) * loss_off.size(), 0},
+      {loss.data(), sizeof(unsigned) * loss.size(), 0},
   };
   size_t off = 0;
   for (auto &p : parts) {
@@ -212,9 +322,11 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   }
   HIP_TRY(h, hipMalloc(&h->dmem, off));
   std::vector<unsigned char> img(off, 0);
-  for (auto &p : parts) memcpy(img.data() + p.off, p.src, p.bytes);
+  for (auto &p : parts)
+    if (p.bytes) memcpy(img.data() + p.off, p.src, p.bytes);
   HIP_TRY(h, hipMemcpy(h->dmem, img.data(), off, hipMemcpyHostToDevice));
   unsigned char *base = (unsigned char *)h->dmem;
+  auto at = [&](int k) { return (const void *)(base + parts[k].off); };
   DevModel &m = h->dm;
   m.B = B;
   m.S = S;
@@ -223,20 +335,26 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.nbr = nbr;
   m.npairs = npairs;
   m.theta = h->theta;
-  m.x = (const double *)(base + parts[0].off);
-  m.invx = (const double *)(base + parts[1].off);
-  m.ct = (const double *)(base + parts[2].off);
-  m.Kd = (const double *)(base + parts[3].off);
-  m.plev = (const double *)(base + parts[4].off);
-  m.invxf = (const float *)(base + parts[5].off);
-  m.ctf = (const float *)(base + parts[6].off);
-  m.Kf = (const float *)(base + parts[7].off);
-  m.kt = (const int *)(base + parts[8].off);
-  m.product = (const int *)(base + parts[9].off);
-  m.KdT = (const double *)(base + parts[10].off);
-  m.ctT = (const double *)(base + parts[11].off);
-  m.KfT = (const float *)(base + parts[12].off);
-  m.ctfT = (const float *)(base + parts[13].off);
+  m.x = (const double *)at(0);
+  m.invx = (const double *)at(1);
+  m.ct = (const double *)at(2);
+  m.Kd = (const double *)at(3);
+  m.plev = (const double *)at(4);
+  m.invxf = (const float *)at(5);
+  m.ctf = (const float *)at(6);
+  m.Kf = (const float *)at(7);
+  m.kt = (const int *)at(8);
+  m.product = (const int *)at(9);
+  m.KdT = (const double *)at(10);
+  m.ctT = (const double *)at(11);
+  m.KfT = (const float *)at(12);
+  m.ctfT = (const float *)at(13);
+  m.xf = (const float *)at(14);
+  m.own = (const short *)at(15);
+  m.tgt_off = (const int *)at(16);
+  m.tgt_ent = (const unsigned *)at(17);
+  m.loss_off = (const int *)at(18);
+  m.loss_ent = (const unsigned *)at(19);
   return FSBM_OK;
 }
 
@@ -248,13 +366,14 @@ void drop_graph(fsbm_coal_t h) {
   h->gkey = GraphKey();
 }
 
-// Workspace for up to npoints points: slots, SoA state, weights, compaction
-// scratch, totals and counters in one allocation.
+// Workspace for up to npoints points: slots, state, weights, compaction
+// scratch, totals, counters, pending-step counters and the exact path's
+// scratch, in one allocation.
 int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   if (npoints <= h->wpoints) return FSBM_OK;
   const int SB = h->S * h->B;
-  const int64_t cap64 =
-      (int64_t)align_up((size_t)npoints + (size_t)kWave * h->dm.nbr, kSlotAlign);
+  const int64_t cap64 = (int64_t)align_up(
+      (size_t)npoints + (size_t)kWave * h->dm.nbr, kSlotAlign);
   if (cap64 > (int64_t)0x7fffff00) return FSBM_EUNSUPPORTED;
   const int cap = (int)cap64;
   const int nblocks = (int)((npoints + kCompactBlock - 1) / kCompactBlock);
@@ -265,6 +384,9 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
     return o;
   };
   const size_t o_state = take(sizeof(double) * (size_t)SB * cap);
+  // the lane kernels read a step's state from one buffer and write the other
+  const size_t o_state2 =
+      h->lane ? take(sizeof(double) * (size_t)SB * cap) : 0;
   const size_t o_wgt = take(sizeof(double) * cap);
   const size_t o_tot = take(sizeof(double) * 4 * (size_t)npoints);
   const size_t o_slot = take(sizeof(int) * cap);
@@ -273,6 +395,8 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   const size_t o_meta = take(sizeof(CompactMeta));
   const size_t o_cnt = take(sizeof(unsigned long long) * 4);
   const size_t o_pend = take(sizeof(int) * cap);
+  const size_t o_keys = h->lane ? take(sizeof(unsigned) * cap) : 0;
+  const size_t o_scr = take(sizeof(double) * (size_t)kSlowThreads * 7 * SB);
   drop_graph(h);
   if (h->wmem) hipFree(h->wmem);
   h->wmem = nullptr;
@@ -284,10 +408,10 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
     return FSBM_ENOMEM;
   }
   unsigned char *b = (unsigned char *)h->wmem;
-  h->wbytes = off;
   h->ws.npoints = npoints;
   h->ws.slot_cap = cap;
   h->ws.state = (double *)(b + o_state);
+  h->ws.state_alt = h->lane ? (double *)(b + o_state2) : nullptr;
   h->ws.wgt = (double *)(b + o_wgt);
   h->ws.tot = (double *)(b + o_tot);
   h->ws.slot_point = (int *)(b + o_slot);
@@ -296,77 +420,44 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   h->ws.meta = (CompactMeta *)(b + o_meta);
   h->ws.counters = (unsigned long long *)(b + o_cnt);
   h->ws.pending = (int *)(b + o_pend);
+  h->ws.keys = h->lane ? (unsigned *)(b + o_keys) : nullptr;
+  h->scratch = (double *)(b + o_scr);
   // pending[] is kept at zero by the kernels after this first clear
   e = hipMemset(h->ws.pending, 0, sizeof(int) * cap);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemset");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
   h->nblocks = nblocks;
   h->wpoints = npoints;
   return FSBM_OK;
 }
 
-int default_steps_per_launch(fsbm_coal_t h) {
-  return h->steps_per_launch > 0 ? h->steps_per_launch : 10;
+int steps_per_launch(fsbm_coal_t h) {
+  return h->steps_per_launch > 0 ? h->steps_per_launch : kDefaultSteps;
 }
-int default_wpb(fsbm_coal_t h) {
+int waves_per_block(fsbm_coal_t h) {
   return h->waves_per_block > 0 ? h->waves_per_block : 1;
 }
+int wave_blocks(fsbm_coal_t h) {
+  return h->wave_blocks > 0 ? h->wave_blocks : kDefaultWaveBlocks;
+}
 
-int event_pair(fsbm_coal_t h, hipEvent_t *a, hipEvent_t *b);
-
-// The launch sequence of one step call (capturable unless profiling).
-int enqueue_call(fsbm_coal_t h, double *N, const double *p, int64_t npoints,
-                 double dt, int nsteps, hipStream_t st, int spl, int wpb) {
-  const DevModel &m = h->dm;
-  DevWork &w = h->ws;
-  HIP_TRY(h, launch_zero_u64(w.counters, 4, st));
-  HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
-                                  w.block_counts, h->nblocks, st));
-  HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, h->nblocks,
-                                 m.nbr, w.meta, st));
-  HIP_TRY(h, launch_compact_gather(N, p, npoints, m.S, m.B, m.plev, m.L,
-                                   w.block_offsets, w.meta, h->nblocks,
-                                   w.slot_point, w.state, w.wgt, w.slot_cap,
-                                   m.x, w.tot, st));
-  HIP_TRY(h, launch_fill_padding(w.meta, w.slot_point, w.slot_cap, st));
-  StepArgs a;
-  a.m = m;
-  a.slot_cap = w.slot_cap;
-  a.slot_point = w.slot_point;
-  a.state = w.state;
-  a.wgt = w.wgt;
-  a.meta = w.meta;
-  a.counters = w.counters;
-  a.pending = w.pending;
-  a.dt = dt;
-  const int max_slots = w.slot_cap;
-  for (int done = 0; done < nsteps; done += spl) {
-    a.nsteps = (nsteps - done) < spl ? (nsteps - done) : spl;
-    if (lane_kernel_supported(m.B, m.S, m.s) &&
-        !(h->flags & FSBM_FLAG_FORCE_WAVE)) {
-      const bool prof = (h->flags & FSBM_FLAG_PROFILE) != 0;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (prof) {
-        const int rc = event_pair(h, &e0, &e1);
-        if (rc != FSBM_OK) return rc;
-        HIP_TRY(h, hipEventRecord(e0, st));
-      }
-      HIP_TRY(h, launch_lane_step(a, h->precision, wpb, max_slots, st));
-      if (prof) HIP_TRY(h, hipEventRecord(e1, st));
-      HIP_TRY(h, launch_slow_steps(a, max_slots, st));
-    } else {
-      h->last_error = "no kernel for this grid yet";
-      return FSBM_EUNSUPPORTED;
-    }
+// ---------------------------------------------------------- profiling
+int event_pair(fsbm_coal_t h, hipEvent_t *a, hipEvent_t *b) {
+  if (h->ev_used == (int)h->ev_start.size()) {
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    h->ev_start.push_back(e0);
+    h->ev_stop.push_back(e1);
   }
-  HIP_TRY(h, launch_scatter(N, npoints, m.S, m.B, w.meta, w.slot_point,
-                            w.state, w.slot_cap, m.x, w.tot, st));
+  *a = h->ev_start[h->ev_used];
+  *b = h->ev_stop[h->ev_used];
+  h->ev_used++;
   return FSBM_OK;
 }
 
-bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
-
-// Collect the durations of the timed launches of the previous call (their
-// stream has been synchronised by the caller or is synchronised here).
+// Collect the durations of the timed launches of the previous call.
 int harvest_events(fsbm_coal_t h) {
   if (h->ev_used == 0) return FSBM_OK;
   HIP_TRY(h, hipEventSynchronize(h->ev_stop[h->ev_used - 1]));
@@ -380,18 +471,198 @@ int harvest_events(fsbm_coal_t h) {
   return FSBM_OK;
 }
 
-int event_pair(fsbm_coal_t h, hipEvent_t *a, hipEvent_t *b) {
-  if (h->ev_used == (int)h->ev_start.size()) {
-    hipEvent_t e0, e1;
-    HIP_TRY(h, hipEventCreate(&e0));
-    HIP_TRY(h, hipEventCreate(&e1));
-    h->ev_start.push_back(e0);
-    h->ev_stop.push_back(e1);
-  }
-  *a = h->ev_start[h->ev_used];
-  *b = h->ev_stop[h->ev_used];
-  h->ev_used++;
+// ------------------------------------------------------ launch sequence
+struct Call {
+  std::vector<fsbm_coal_t> hs;
+  std::vector<double *> N;
+  std::vector<const double *> p;
+  std::vector<int64_t> npts;
+  double dt = 0.0;
+  int nsteps = 0;
+  bool wave = false;  // one-point-per-wave kernel for every grid
+  int spl = 0, wpb = 0, blocks = 0;
+};
+
+int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
+                     int64_t npoints, bool aos, hipStream_t st) {
+  const DevModel &m = h->dm;
+  DevWork &w = h->ws;
+  HIP_TRY(h, launch_zero_u64(w.counters, 4, st));
+  HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
+                                  w.block_counts, h->nblocks, st));
+  HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, h->nblocks,
+                                 m.nbr, w.meta, st));
+  // one point per lane: slots are ordered by top active bin and mass
+  // within chunks before the state is loaded (see compact.hip)
+  unsigned *keys = aos ? nullptr : w.keys;
+  HIP_TRY(h, launch_compact_gather(N, p, npoints, m.S, m.B, m.plev, m.L,
+                                   w.block_offsets, w.meta, h->nblocks,
+                                   w.slot_point, w.state, w.wgt, w.slot_cap,
+                                   m.x, w.tot, aos ? 1 : 0, keys, m.theta,
+                                   st));
+  HIP_TRY(h, launch_fill_padding(w.meta, w.slot_point, keys, w.slot_cap, st));
+  if (keys)
+    HIP_TRY(h, launch_compact_sort_load(N, w.meta, keys, w.slot_point, w.wgt,
+                                        m.S * m.B, w.state, w.slot_cap, st));
   return FSBM_OK;
+}
+
+int enqueue_call(const Call &c, hipStream_t st) {
+  fsbm_coal_t h0 = c.hs[0];
+  for (size_t g = 0; g < c.hs.size(); ++g)
+    RC_TRY(enqueue_prologue(c.hs[g], c.N[g], c.p[g], c.npts[g], c.wave, st));
+  const bool prof = (h0->flags & FSBM_FLAG_PROFILE) != 0;
+  StepArgs la{};
+  WaveArgs wa{};
+  if (!c.wave) {
+    const DevWork &w = h0->ws;
+    la.m = h0->dm;
+    la.slot_cap = w.slot_cap;
+    la.slot_point = w.slot_point;
+    la.state = w.state;
+    la.wgt = w.wgt;
+    la.meta = w.meta;
+    la.counters = w.counters;
+    la.pending = w.pending;
+    la.dt = c.dt;
+  } else {
+    wa.ngrids = (int)c.hs.size();
+    int sbmax = 0;
+    for (size_t g = 0; g < c.hs.size(); ++g) {
+      fsbm_coal_t h = c.hs[g];
+      WaveGrid &G = wa.g[g];
+      G.m = h->dm;
+      G.slot_point = h->ws.slot_point;
+      G.state = h->ws.state;
+      G.wgt = h->ws.wgt;
+      G.meta = h->ws.meta;
+      G.pending = h->ws.pending;
+      G.slot_cap = h->ws.slot_cap;
+      sbmax = std::max(sbmax, h->S * h->B);
+    }
+    // the first handle is the widest grid of the call (see step_multi), so
+    // its exact-path scratch fits every grid
+    wa.counters = h0->ws.counters;
+    wa.scratch = h0->scratch;
+    wa.scratch_sb = sbmax;
+    wa.dt = c.dt;
+  }
+  // lane kernels: a launch of n steps leaves the state in the buffer it
+  // started from when n is even, in the other one when n is odd
+  double *lane_cur = h0->ws.state, *lane_alt = h0->ws.state_alt;
+  for (int done = 0; done < c.nsteps; done += c.spl) {
+    const int n = std::min(c.spl, c.nsteps - done);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+      RC_TRY(event_pair(h0, &e0, &e1));
+      HIP_TRY(h0, hipEventRecord(e0, st));
+    }
+    if (!c.wave) {
+      la.nsteps = n;
+      la.steps_left = c.nsteps - done;
+      la.state = lane_cur;
+      la.state_alt = lane_alt;
+      HIP_TRY(h0, launch_lane_step(la, h0->precision, c.wpb,
+                                   h0->ws.slot_cap, st));
+      if (n & 1) std::swap(lane_cur, lane_alt);
+    } else {
+      wa.nsteps = n;
+      wa.steps_left = c.nsteps - done;
+      HIP_TRY(h0, launch_wave_step(wa, h0->precision, c.blocks, st));
+    }
+    if (prof) HIP_TRY(h0, hipEventRecord(e1, st));
+  }
+  // points the fast kernels handed over finish the call on the exact path
+  // (their state is valid in both lane buffers)
+  if (c.nsteps > 0) {
+    if (!c.wave) {
+      la.state = lane_cur;
+      la.state_alt = lane_alt;
+      HIP_TRY(h0, launch_slow_steps(la, h0->ws.slot_cap, st));
+    } else {
+      HIP_TRY(h0, launch_wave_slow(wa, st));
+    }
+  }
+  for (size_t g = 0; g < c.hs.size(); ++g) {
+    fsbm_coal_t h = c.hs[g];
+    const DevModel &m = h->dm;
+    double *final_state = c.wave ? h->ws.state : lane_cur;
+    HIP_TRY(h, launch_scatter(c.N[g], c.npts[g], m.S, m.B, h->ws.meta,
+                              h->ws.slot_point, final_state, h->ws.slot_cap,
+                              m.x, h->ws.tot, c.wave ? 1 : 0, st));
+  }
+  return FSBM_OK;
+}
+
+// Enqueue a call, through the graph cache of its first handle when the
+// stream allows capture.
+int run_call(const Call &c, void *stream) {
+  fsbm_coal_t h0 = c.hs[0];
+  hipStream_t st = (hipStream_t)stream;
+  for (auto h : c.hs) {
+    RC_TRY(harvest_events(h));
+    h->last_stream = st;
+  }
+  bool use_graph = st != nullptr;
+  for (auto h : c.hs)
+    if (h->flags & (FSBM_FLAG_NO_GRAPH | FSBM_FLAG_PROFILE)) use_graph = false;
+  if (!use_graph) return enqueue_call(c, st);
+  GraphKey key;
+  for (size_t g = 0; g < c.hs.size(); ++g) {
+    key.ptrs.push_back(c.N[g]);
+    key.ptrs.push_back(c.p[g]);
+    key.npts.push_back(c.npts[g]);
+    key.handles.push_back(c.hs[g]);
+  }
+  key.dt = c.dt;
+  key.nsteps = c.nsteps;
+  key.stream = stream;
+  key.spl = c.spl;
+  key.wpb = c.wpb;
+  key.blocks = c.blocks;
+  if (!(h0->gexec && key == h0->gkey)) {
+    drop_graph(h0);
+    HIP_TRY(h0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_call(c, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != FSBM_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(h0, e, "hipStreamEndCapture");
+    h0->graph = g;
+    const hipError_t ei =
+        hipGraphInstantiate(&h0->gexec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      drop_graph(h0);
+      return hip_fail(h0, ei, "hipGraphInstantiate");
+    }
+    h0->gkey = key;
+  }
+  HIP_TRY(h0, hipGraphLaunch(h0->gexec, st));
+  return FSBM_OK;
+}
+
+int check_step_args(fsbm_coal_t h, const double *N, const double *p,
+                    int64_t npoints, double dt, int nsteps) {
+  if (!h || npoints < 0 || nsteps < 0 || !isfinite(dt) || !(dt > 0.0))
+    return FSBM_EINVAL;
+  if (npoints > 0 && (!N || !p)) return FSBM_EINVAL;
+  return FSBM_OK;
+}
+
+int debug_check(fsbm_coal_t h, const double *N, int64_t npoints,
+                hipStream_t st) {
+  int *bad = h->ws.block_counts;  // scratch int, rewritten by compaction
+  int hbad = 0;
+  HIP_TRY(h, hipMemcpyAsync(bad, &hbad, sizeof(int), hipMemcpyHostToDevice,
+                            st));
+  HIP_TRY(h, launch_check_state(N, npoints * h->S * h->B, bad, st));
+  HIP_TRY(h, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost,
+                            st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  return hbad ? FSBM_EDOMAIN : FSBM_OK;
 }
 
 }  // namespace
@@ -423,16 +694,16 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
     return FSBM_EINVAL;
   if (nbins > kMaxBins || nlevels - 1 > kMaxBuckets) return FSBM_EUNSUPPORTED;
   if (o.s < 1 || !finite_pos(o.x1_g) || !(o.theta >= 0.0) ||
-      !isfinite(o.theta) || (o.precision != FSBM_FP64 &&
-                             o.precision != FSBM_FP32C) ||
+      !isfinite(o.theta) ||
+      (o.precision != FSBM_FP64 && o.precision != FSBM_FP32C) ||
       o.steps_per_launch < 0)
     return FSBM_EINVAL;
   for (int l = 0; l < nlevels; ++l)
     if (!isfinite(p_levels_hpa[l])) return FSBM_EINVAL;
   for (int l = 0; l + 1 < nlevels; ++l)
     if (!(p_levels_hpa[l] > p_levels_hpa[l + 1])) return FSBM_EINVAL;
-  const size_t nt = (size_t)nspecies * (nspecies + 1) / 2 * nlevels * nbins *
-                    nbins;
+  const size_t nt =
+      (size_t)nspecies * (nspecies + 1) / 2 * nlevels * nbins * nbins;
   for (size_t q = 0; q < nt; ++q)
     if (!(kernel_tables[q] >= 0.0) || !isfinite(kernel_tables[q]))
       return FSBM_EINVAL;
@@ -464,6 +735,8 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
   h->flags = o.flags;
   h->steps_per_launch = o.steps_per_launch;
   h->product = product;
+  h->lane = lane_kernel_supported(nbins, nspecies, o.s) &&
+            !(o.flags & FSBM_FLAG_FORCE_WAVE);
   read_tune_cache(h);
   const int rc = build_model(h, kernel_tables, p_levels_hpa);
   if (rc != FSBM_OK) {
@@ -477,90 +750,190 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
 int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
                    int64_t npoints, double dt_s, int32_t nsteps,
                    void *stream) {
-  if (!h || npoints < 0 || nsteps < 0 || !isfinite(dt_s) || !(dt_s > 0.0))
-    return FSBM_EINVAL;
+  RC_TRY(check_step_args(h, N, p_hpa, npoints, dt_s, nsteps));
   if (npoints == 0 || nsteps == 0) return FSBM_OK;
-  if (!N || !p_hpa) return FSBM_EINVAL;
-  if (!lane_kernel_supported(h->B, h->S, h->s) ||
-      (h->flags & FSBM_FLAG_FORCE_WAVE)) {
-    h->last_error = "no kernel for this grid yet";
-    return FSBM_EUNSUPPORTED;
-  }
-  hipStream_t st = (hipStream_t)stream;
   HIP_TRY(h, hipSetDevice(h->device));
-  int rc = ensure_workspace(h, npoints);
-  if (rc != FSBM_OK) return rc;
-  if (h->flags & FSBM_FLAG_DEBUG_CHECKS) {
-    int *bad = (int *)h->ws.block_counts;  // scratch int, rewritten later
-    int hbad = 0;
-    HIP_TRY(h, hipMemcpyAsync(bad, &hbad, sizeof(int), hipMemcpyHostToDevice,
-                              st));
-    HIP_TRY(h, launch_check_state(N, npoints * h->S * h->B, bad, st));
-    HIP_TRY(h, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost,
-                              st));
-    HIP_TRY(h, hipStreamSynchronize(st));
-    if (hbad) return FSBM_EDOMAIN;
-  }
-  const int spl = default_steps_per_launch(h);
-  const int wpb = default_wpb(h);
-  rc = harvest_events(h);
-  if (rc != FSBM_OK) return rc;
-  h->last_stream = st;
+  RC_TRY(ensure_workspace(h, npoints));
+  if (h->flags & FSBM_FLAG_DEBUG_CHECKS)
+    RC_TRY(debug_check(h, N, npoints, (hipStream_t)stream));
+  Call c;
+  c.hs = {h};
+  c.N = {N};
+  c.p = {p_hpa};
+  c.npts = {npoints};
+  c.dt = dt_s;
+  c.nsteps = nsteps;
+  c.wave = !h->lane;
+  c.spl = steps_per_launch(h);
+  c.wpb = waves_per_block(h);
+  c.blocks = wave_blocks(h);
   h->last_npoints = npoints;
-  const bool use_graph = st != nullptr &&
-                         !(h->flags & (FSBM_FLAG_NO_GRAPH | FSBM_FLAG_PROFILE));
-  if (!use_graph) return enqueue_call(h, N, p_hpa, npoints, dt_s, nsteps, st,
-                                      spl, wpb);
-  GraphKey key;
-  key.N = N;
-  key.p = p_hpa;
-  key.npoints = npoints;
-  key.dt = dt_s;
-  key.nsteps = nsteps;
-  key.stream = stream;
-  key.spl = spl;
-  key.wpb = wpb;
-  if (!(h->gexec && key == h->gkey)) {
-    drop_graph(h);
-    HIP_TRY(h, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_call(h, N, p_hpa, npoints, dt_s, nsteps, st, spl, wpb);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
-    if (rc != FSBM_OK) {
-      if (g) hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
-    h->graph = g;
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      drop_graph(h);
-      return hip_fail(h, e, "hipGraphInstantiate");
-    }
-    h->gkey = key;
-  }
-  HIP_TRY(h, hipGraphLaunch(h->gexec, st));
-  return FSBM_OK;
+  return run_call(c, stream);
 }
 
 int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
                          double *const *N, const double *const *p_hpa,
                          const int64_t *npoints, double dt_s, int32_t nsteps,
                          void *stream) {
-  if (!hs || ngrids < 0 || !N || !p_hpa || !npoints) return FSBM_EINVAL;
+  if (!hs || ngrids < 0 || (ngrids > 0 && (!N || !p_hpa || !npoints)))
+    return FSBM_EINVAL;
+  if (ngrids > kMaxGrids) return FSBM_EUNSUPPORTED;
+  Call c;
   for (int g = 0; g < ngrids; ++g) {
-    const int rc = fsbm_coal_step(hs[g], N[g], p_hpa[g], npoints[g], dt_s,
-                                  nsteps, stream);
-    if (rc != FSBM_OK) return rc;
+    RC_TRY(check_step_args(hs[g], N[g], p_hpa[g], npoints[g], dt_s, nsteps));
+    if (hs[g]->precision != hs[0]->precision) return FSBM_EINVAL;
+    if (hs[g]->device != hs[0]->device) return FSBM_EINVAL;
+    if (hs[g]->S * hs[g]->B > kWave * kMaxOwn) return FSBM_EUNSUPPORTED;
+    for (int k = 0; k < g; ++k)
+      if (hs[k] == hs[g]) return FSBM_EINVAL;  // one workspace per grid
+    if (npoints[g] == 0) continue;
+    c.hs.push_back(hs[g]);
+    c.N.push_back(N[g]);
+    c.p.push_back(p_hpa[g]);
+    c.npts.push_back(npoints[g]);
   }
-  return FSBM_OK;
+  if (c.hs.empty() || nsteps == 0) return FSBM_OK;
+  HIP_TRY(c.hs[0], hipSetDevice(c.hs[0]->device));
+  // the widest grid goes first: its exact-path scratch serves every grid
+  size_t widest = 0;
+  for (size_t g = 1; g < c.hs.size(); ++g)
+    if (c.hs[g]->S * c.hs[g]->B > c.hs[widest]->S * c.hs[widest]->B)
+      widest = g;
+  std::swap(c.hs[0], c.hs[widest]);
+  std::swap(c.N[0], c.N[widest]);
+  std::swap(c.p[0], c.p[widest]);
+  std::swap(c.npts[0], c.npts[widest]);
+  for (size_t g = 0; g < c.hs.size(); ++g) {
+    fsbm_coal_t h = c.hs[g];
+    RC_TRY(ensure_workspace(h, c.npts[g]));
+    if (h->flags & FSBM_FLAG_DEBUG_CHECKS)
+      RC_TRY(debug_check(h, c.N[g], c.npts[g], (hipStream_t)stream));
+    h->last_npoints = c.npts[g];
+  }
+  c.dt = dt_s;
+  c.nsteps = nsteps;
+  c.wave = true;
+  c.spl = steps_per_launch(c.hs[0]);
+  c.wpb = 1;
+  c.blocks = wave_blocks(c.hs[0]);
+  return run_call(c, stream);
 }
 
 int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
-  (void)npoints_hint;
-  (void)stream;
-  if (!h) return FSBM_EINVAL;
-  return FSBM_OK;
+  if (!h || npoints_hint < 0) return FSBM_EINVAL;
+  HIP_TRY(h, hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = std::min<int64_t>(std::max<int64_t>(npoints_hint, 4096),
+                                      1 << 20);
+  const int B = h->B, S = h->S, SB = S * B;
+  // synthetic states: exponential spectra with point-dependent mean mass,
+  // pressures spread over the tabulated range
+  std::vector<double> N0((size_t)P * SB), p0(P);
+  const double pmax = h->L > 1 ? 1000.0 : 1000.0;
+  for (int64_t pt = 0; pt < P; ++pt) {
+    const double xbar = h->x[0] * pow(2.0, 3.0 + (double)(pt % 97) / 16.0);
+    for (int a = 0; a < S; ++a)
+      for (int k = 0; k < B; ++k) {
+        const double xx = h->x[k];
+        const double mass = 1e-6 * xx / xbar * exp(-xx / xbar) /
+                            (double)(a + 1);
+        N0[(size_t)pt * SB + a * B + k] = mass / xx;
+      }
+    p0[pt] = pmax - 500.0 * (double)(pt % 50) / 49.0;
+  }
+  double *dN = nullptr, *dN0 = nullptr, *dp = nullptr;
+  HIP_TRY(h, hipMalloc(&dN, sizeof(double) * N0.size()));
+  HIP_TRY(h, hipMalloc(&dN0, sizeof(double) * N0.size()));
+  HIP_TRY(h, hipMalloc(&dp, sizeof(double) * P));
+  auto cleanup = [&]() {
+    hipFree(dN);
+    hipFree(dN0);
+    hipFree(dp);
+  };
+  if (hipMemcpy(dN0, N0.data(), sizeof(double) * N0.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dp, p0.data(), sizeof(double) * P, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    cleanup();
+    return FSBM_EHIP;
+  }
+  struct Cand {
+    int spl, wpb, blocks;
+  };
+  std::vector<Cand> cands;
+  const int nsteps = 20;
+  if (h->lane) {
+    for (int spl : {1, 5, 10, 20})
+      for (int wpb : {1, 2}) cands.push_back({spl, wpb, 0});
+  } else {
+    for (int spl : {5, 10, 20})
+      for (int blocks : {1024, 2048, 4096, 8192})
+        cands.push_back({spl, 1, blocks});
+  }
+  const int save_flags = h->flags;
+  h->flags |= FSBM_FLAG_NO_GRAPH;
+  h->flags &= ~FSBM_FLAG_PROFILE;
+  std::vector<double> ref, got;
+  double best_ms = 1e300;
+  Cand best = cands[0];
+  int rc = FSBM_OK;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  for (size_t ci = 0; ci < cands.size() && rc == FSBM_OK; ++ci) {
+    const Cand &cd = cands[ci];
+    h->steps_per_launch = cd.spl;
+    h->waves_per_block = cd.wpb;
+    h->wave_blocks = cd.blocks;
+    double ms_best = 1e300;
+    for (int rep = 0; rep < 2 && rc == FSBM_OK; ++rep) {
+      if (hipMemcpyAsync(dN, dN0, sizeof(double) * N0.size(),
+                         hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        rc = FSBM_EHIP;
+        break;
+      }
+      hipEventRecord(e0, st);
+      rc = fsbm_coal_step(h, dN, dp, P, 2.0, nsteps, stream);
+      hipEventRecord(e1, st);
+      if (rc != FSBM_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = FSBM_EHIP;
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_best = std::min(ms_best, (double)ms);
+    }
+    if (rc != FSBM_OK) break;
+    // every candidate must reproduce the first one bit for bit (the launch
+    // shape does not change the arithmetic)
+    got.resize(N0.size());
+    if (hipMemcpy(got.data(), dN, sizeof(double) * got.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = FSBM_EHIP;
+      break;
+    }
+    if (ci == 0) {
+      ref = got;
+    } else if (memcmp(ref.data(), got.data(),
+                      sizeof(double) * got.size()) != 0) {
+      continue;  // rejected
+    }
+    if (ms_best < best_ms) {
+      best_ms = ms_best;
+      best = cd;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  cleanup();
+  h->flags = save_flags;
+  h->steps_per_launch = best.spl;
+  h->waves_per_block = best.wpb;
+  h->wave_blocks = best.blocks;
+  drop_graph(h);
+  if (rc == FSBM_OK) write_tune_cache(h);
+  return rc;
 }
 
 int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
@@ -580,16 +953,12 @@ int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
 int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   if (!h || !out) return FSBM_EINVAL;
   memset(out, 0, sizeof(*out));
-  out->kernel = (lane_kernel_supported(h->B, h->S, h->s) &&
-                 !(h->flags & FSBM_FLAG_FORCE_WAVE))
-                    ? 0
-                    : 1;
-  out->steps_per_launch = default_steps_per_launch(h);
-  out->waves_per_block = default_wpb(h);
+  out->kernel = h->lane ? 0 : 1;
+  out->steps_per_launch = steps_per_launch(h);
+  out->waves_per_block = h->lane ? waves_per_block(h) : 1;
   if (h->wpoints < 0) return FSBM_OK;
   HIP_TRY(h, hipStreamSynchronize(h->last_stream));
-  const int rc = harvest_events(h);
-  if (rc != FSBM_OK) return rc;
+  RC_TRY(harvest_events(h));
   out->kernel_launches = h->prof_launches;
   out->kernel_ms = h->prof_ms;
   unsigned long long c[4];

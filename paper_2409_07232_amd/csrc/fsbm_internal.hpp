@@ -8,12 +8,19 @@
 
 namespace fsbm {
 
+// ln 2 in FP32, shared by the host tables and the kernels
+constexpr float kLn2f = 0.69314718055994530942f;
+
+
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxBins = 512;
 constexpr int kMaxBuckets = 8;     // pressure brackets (levels - 1), capped
 constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
+constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
+constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
+constexpr int kSlowThreads = 4096; // exact-path threads (global scratch)
 // Empty-neighbour guard of the flux fraction: x1 >= ln(1e-60).
 constexpr double kX1Floor = -138.15510557964274;
 
@@ -24,6 +31,7 @@ struct DevModel {
   int npairs;     // S (S + 1) / 2 species pairs
   double theta;
   const double *x;      // [B] bin masses (g)
+  const float *xf;      // [B] bin masses rounded to FP32
   const double *invx;   // [B] 1 / x
   const float *invxf;   // [B] 1 / x rounded to FP32
   const int *kt;        // [B*B] target bin of pair (i, j), -1 = off grid
@@ -38,8 +46,28 @@ struct DevModel {
   const double *KdT;
   const float *KfT;
   const double *ctT;
-  const float *ctfT;
+  const float *ctfT;  // [j][i][2]: FP32 Courant number c and c * kLn2f
+  // one-point-per-wave kernel: bins owned by each lane ([64][kMaxOwn], -1
+  // padded), and per bin the packed pairs that target it and the packed
+  // partners it loses mass to (CSR)
+  const short *own;
+  const int *tgt_off;
+  const unsigned *tgt_ent;
+  const int *loss_off;
+  const unsigned *loss_ent;
 };
+
+// Packed bin pair (a,i) x (b,j) in canonical order (a <= b, i <= j if a == b):
+// i and j (9 bits each), a and b (3 bits each), and flags.
+constexpr unsigned kEntTA = 1u << 24;    // (a,i) is the pair's target bin
+constexpr unsigned kEntTB = 1u << 25;    // (b,j) is the pair's target bin
+constexpr unsigned kEntSideB = 1u << 26; // loss entry: the owner is (b,j)
+constexpr unsigned kEntSelf = 1u << 27;  // loss entry: (a,i) == (b,j)
+__host__ __device__ __forceinline__ unsigned pack_pair(int a, int i, int b,
+                                                       int j) {
+  return (unsigned)i | ((unsigned)j << 9) | ((unsigned)a << 18) |
+         ((unsigned)b << 21);
+}
 
 // Compaction results, written on the device (graph-capturable: no host
 // round trip).  Slots of one pressure bracket are contiguous and padded to a
@@ -58,6 +86,11 @@ __host__ __device__ __forceinline__ size_t state_index(int q, int slot,
                                                        int SB) {
   return ((size_t)(slot >> 6) * SB + q) * 64 + (slot & 63);
 }
+// The one-point-per-wave kernel keeps each point's bins contiguous instead.
+__host__ __device__ __forceinline__ size_t state_index_aos(int q, int slot,
+                                                           int SB) {
+  return (size_t)slot * SB + q;
+}
 
 // Per-call device workspace of one handle.
 struct DevWork {
@@ -65,13 +98,38 @@ struct DevWork {
   int slot_cap;          // capacity of the slot arrays (stride of state)
   int *slot_point;       // [slot_cap] point index or -1 (padding)
   double *state;         // tiled SoA [slot/64][S*B][slot%64] bin numbers N
+  double *state_alt;     // same shape: second buffer of the lane kernels
   double *wgt;           // [slot_cap] pressure-interpolation weight
   CompactMeta *meta;     // device
   int *block_counts;     // [nblocks_compact][kMaxBuckets]
   int *block_offsets;    // same shape, exclusive scan
   double *tot;           // [4][npoints]: mass before/after, number b/a
-  int *pending;          // [slot_cap] steps left for the exact FP64 path
+  unsigned *keys;        // [slot_cap] sort keys (lane kernels) or null
+  int *pending;          // [slot_cap] steps of the call left for the exact
+                         // FP64 path (0 = point still on the fast path)
   unsigned long long *counters;  // [4]: pair evals, limiter, fallback, -
+};
+
+// One grid of a one-point-per-wave launch (a call may cover several grids).
+struct WaveGrid {
+  DevModel m;
+  const int *slot_point;
+  double *state;  // [slot][S*B]
+  const double *wgt;
+  const CompactMeta *meta;
+  int *pending;
+  int slot_cap;
+};
+
+struct WaveArgs {
+  WaveGrid g[kMaxGrids];
+  int ngrids;
+  unsigned long long *counters;
+  double *scratch;  // exact path: [kSlowThreads][7 * max S*B]
+  int scratch_sb;   // max S*B the scratch was sized for
+  double dt;
+  int nsteps;       // steps in this launch
+  int steps_left;   // steps of the call left when this launch starts
 };
 
 // Arguments of the step kernels.
@@ -79,13 +137,16 @@ struct StepArgs {
   DevModel m;
   int slot_cap;
   const int *slot_point;
-  double *state;
+  double *state;      // state at the start of the launch
+  double *state_alt;  // second buffer: a step reads one and writes the
+                      // other (kernels that update in place ignore it)
   const double *wgt;
   const CompactMeta *meta;
   int *pending;         // [slot_cap]: > 0 where a lane left the fast path
   unsigned long long *counters;
   double dt;
   int nsteps;           // steps in this launch
+  int steps_left;       // steps of the call left when this launch starts
 };
 
 // --- host-side launchers (defined in the kernel translation units) -------
@@ -103,14 +164,21 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  const CompactMeta *meta, int nblocks,
                                  int *slot_point, double *state,
                                  double *wgt, int slot_cap,
-                                 const double *x, double *tot,
+                                 const double *x, double *tot, int aos,
+                                 unsigned *keys, double theta,
                                  hipStream_t st);
 hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
-                               int slot_cap, hipStream_t st);
+                               unsigned *keys, int slot_cap, hipStream_t st);
+// With keys: order the compacted slots by key within chunks, then load the
+// state (tiled layout) in that order.
+hipError_t launch_compact_sort_load(const double *N, const CompactMeta *meta,
+                                    const unsigned *keys, int *slot_point,
+                                    double *wgt, int SB, double *state,
+                                    int slot_cap, hipStream_t st);
 hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
                           const CompactMeta *meta, const int *slot_point,
                           const double *state, int slot_cap, const double *x,
-                          double *tot, hipStream_t st);
+                          double *tot, int aos, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 hipError_t launch_check_state(const double *N, int64_t n, int *bad,
                               hipStream_t st);
@@ -120,8 +188,16 @@ bool lane_kernel_supported(int B, int S, int s);
 hipError_t launch_lane_step(const StepArgs &a, int precision,
                             int waves_per_block, int max_slots,
                             hipStream_t st);
+// One-point-per-wave kernels (any species set and grid), over one or more
+// grids, and their exact FP64 path.
+hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
+                            hipStream_t st);
+hipError_t launch_wave_slow(const WaveArgs &a, hipStream_t st);
+
 // Exact FP64 steps (with the positivity limiter) for every slot whose fast
-// kernel stopped on an over-demand bound; clears pending[].
+// kernel stopped on an over-demand bound: once a point leaves the fast path
+// it takes every remaining step of the call on the exact path, so results do
+// not depend on how the call is cut into launches.  Clears pending[].
 hipError_t launch_slow_steps(const StepArgs &a, int max_slots,
                              hipStream_t st);
 

@@ -6,17 +6,18 @@
 // Layout and mapping (gfx950):
 //  * compacted cloudy points sit in a structure-of-arrays workspace
 //    state[bin][slot], so a wave reads and writes each bin of its 64 points
-//    as one contiguous 512-byte row;
+//    as one contiguous 512-byte row; there are two such buffers and each
+//    step reads one and writes the other;
 //  * the pair loop is wave-uniform: rows j (the larger bin) run over the
 //    union of the wave's active bins, in descending order; columns i < j are
 //    unrolled.  Kernel-table entries, Courant numbers and bin masses are
 //    therefore scalar operands, and every per-pair register access has a
 //    static index (the column bin i);
-//  * per lane, the masses and the losses of column bins stay in VGPRs; the
-//    two per-row updates of bins j and j+1 go to a small per-lane LDS array
-//    laid out [bin][lane] (bank-conflict free);
+//  * per lane, the masses and the losses of column bins stay in VGPRs;
 //  * descending rows complete each bin's losses before its own row ends, so
-//    the positivity-limiter test of a bin is taken right there;
+//    the positivity-limiter test of a bin is taken right there, and bin j+1
+//    is final after row j: its update is written out during the sweep and
+//    only one gain is carried from row to row (no LDS);
 //  * every wave lies in one pressure bracket (the compaction pads brackets to
 //    whole waves): the per-pair kernel interpolation is one FMA with two
 //    scalar table operands.
@@ -30,7 +31,7 @@
 //    family, TwoSum error capture), then carried into an FP64 update of the
 //    FP64 state.
 // A lane whose over-demand test fires leaves the fast kernel; the exact FP64
-// path (slow_path.hpp) finishes that launch's steps for it.
+// path (slow_path.hpp) takes the rest of the call's steps for it.
 #include <float.h>
 
 #include "device_common.hpp"
@@ -74,10 +75,20 @@ __device__ __forceinline__ bool bit_of(uint32_t lo, uint32_t hi, int k) {
 }
 
 // ---------------------------------------------------------- FP64 kernel
+// Both lane kernels read the step's state from one buffer and write the
+// updated bins to the other.  Bin k's net change is complete once the rows
+// above it and the row below it are done: its gains come from row k (mass
+// arriving from smaller partners) and row k-1 (flux and self-pair mass), its
+// losses as the smaller partner from the rows above.  The descending sweep
+// therefore finishes bin j+1 right after row j, carrying only bin j+1's
+// own-row gain from one row to the next; nothing is staged in LDS.  A lane
+// that stops for the exact path copies its untouched state over, so it is
+// valid in both buffers.
 template <int B, int WPB>
-__global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
+__global__ void __launch_bounds__(kWave *WPB)
+    __attribute__((amdgpu_waves_per_eu(B <= 33 ? 2 : 1))) lane_step_f64(
+        StepArgs a) {
   constexpr int nthr = kWave * WPB;
-  __shared__ double lds_g[B * nthr];  // [bin][thread] gains of bins
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int slot = blockIdx.x * nthr + tid;
@@ -85,7 +96,8 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
   const int wave_first = uniform(slot & ~(kWave - 1));
   if (wave_first >= nslots) return;
   const int br = wave_bracket(a.meta, wave_first, a.m.nbr);
-  bool live = slot < nslots && a.slot_point[slot] >= 0;
+  // a slot handed to the exact path earlier in the call stays there
+  bool live = slot < nslots && a.slot_point[slot] >= 0 && a.pending[slot] == 0;
   const double w = live ? a.wgt[slot] : 0.0;
   // tables transposed to [j][i]: the columns of row j are contiguous
   const double *__restrict__ Kd = a.m.KdT + (size_t)br * B * B * 2;
@@ -95,17 +107,19 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
   // power-of-two scalings of products with x_1
   const double x1 = ldc(a.m.x);
   // bin k of this lane's point: stw[k * 64 + lane] (wave tile, uniform base)
-  double *const stw = a.state + (size_t)wave_first * B;
-  double *G = lds_g + tid;
+  double *const stw0 = a.state + (size_t)wave_first * B;
+  double *const stw1 = a.state_alt + (size_t)wave_first * B;
   const double theta = a.m.theta, dt = a.dt;
   unsigned long long npairs = 0;
 
   for (int step = 0; step < a.nsteps; ++step) {
-    // Opaque per-step copy of the wave's base pointer: keeps the compiler
+    // Opaque per-step copies of the wave's base pointers: keep the compiler
     // from hoisting B per-lane 64-bit addresses out of the step loop (the
-    // loads use a scalar base, one lane offset and immediate offsets).
-    double *sb = stw;
+    // accesses use a scalar base, one lane offset and immediate offsets).
+    double *sb = (step & 1) ? stw1 : stw0;  // read
+    double *so = (step & 1) ? stw0 : stw1;  // written
     asm volatile("" : "+s"(sb));
+    asm volatile("" : "+s"(so));
     // S1/S2: masses, FP64 total (bins ascending), activity.
     BinsD<B> Mt;
     double Mtot = 0.0;
@@ -126,7 +140,6 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
       act |= (uint64_t)ak << k;
       Mt.set(k, ak ? Mk : 0.0);
       L.set(k, 0.0);
-      G[k * nthr] = 0.0;
     }
     const uint64_t uni = wave_or64(act);
     const int lo = uniform(uni ? (int)__builtin_ctzll(uni) : 0);
@@ -135,88 +148,111 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f64(StepArgs a) {
     const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
     bool flag = false;
     unsigned step_pairs = 0;
+    // S6 for bin k: FP64 update, negative round-off clamped, back to
+    // numbers, into the other buffer
+    auto finish = [&](int k, double g, double Nk) {
+      const double Mk = ldexp(__dmul_rn(Nk, x1), k);
+      double Mn = Mk + (g - L.get(k));
+      Mn = Mn < 0.0 ? 0.0 : Mn;
+      if (live) so[k * kWave + lane] = ldexp(Mn / x1, -k);
+    };
+    double g = 0.0;  // gain of bin j+1 from its own row, carried down
+    // state of bin j+1, loaded one row ahead of its update (rows run over
+    // the union [lo, hi] of the wave's active bins; bins lo..hi+1 change)
+    double Nnext = (hi + 1 <= B - 1) ? sb[(hi + 1) * kWave + lane] : 0.0;
 
     // S3/S4: rows j descending, columns i < j unrolled.
     for (int j = hi; j >= lo; --j) {
-      if (!bit_of(uni_lo, uni_hi, j)) continue;
-      // columns to visit: i < j with bin i active in some lane of the wave
-      const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
-      const uint32_t cl = uni_lo & (uint32_t)below_mask;
-      const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
-      const double Mtj = Mt.get(j);
-      const double qj = dt * (Mtj * ldc(ixg + j));  // dt N_j, 0 if inactive
-      const bool has_flux = j <= B - 2;
-      const double lnj1 = has_flux ? log(Mt.get(j + 1)) : 0.0;  // -inf if 0
-      const double *Kj = Kd + (size_t)j * B * 2;  // row j: [i][2]
-      const double *cj = ctab + (size_t)j * B;
-      double netj = 0.0, fout = 0.0, dneg = 0.0;
+      const double Nj1 = Nnext;
+      Nnext = sb[j * kWave + lane];
+      double gj = 0.0;  // gain of bin j from row j
+      if (bit_of(uni_lo, uni_hi, j)) {
+        // columns to visit: i < j with bin i active in some lane
+        const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+        const uint32_t cl = uni_lo & (uint32_t)below_mask;
+        const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
+        const double Mtj = Mt.get(j);
+        const double qj = dt * (Mtj * ldc(ixg + j));  // dt N_j, 0 if inactive
+        const bool has_flux = j <= B - 2;
+        const double lnj1 = has_flux ? log(Mt.get(j + 1)) : 0.0;  // -inf if 0
+        const double *Kj = Kd + (size_t)j * B * 2;  // row j: [i][2]
+        const double *cj = ctab + (size_t)j * B;
+        double netj = 0.0, fout = 0.0, dneg = 0.0;
 #pragma unroll
-      for (int i = 0; i < B - 1; ++i) {
-        if (!bit_of(cl, ch, i)) continue;
-        const double *e = Kj + i * 2;
-        const double K = fma(ldc(e + 1), w, ldc(e));
-        // A = C x_i = dt K N_j M_i, B = C x_j = A 2^(j-i)
-        const double A = (qj * K) * Mt.get(i);
-        const double Bm = ldexp(A, j - i);
-        const double Sm = A + Bm;
-        double F = 0.0;
-        if (has_flux) {
-          const double den = fmax(Mtj + Sm, DBL_MIN);
-          const double x1f = fmax(lnj1 - log(den), kX1Floor);
-          F = flux_fraction_f64(ldc(cj + i), x1f) * Sm;
+        for (int i = 0; i < B - 1; ++i) {
+          if (!bit_of(cl, ch, i)) continue;
+          const double *e = Kj + i * 2;
+          const double K = fma(ldc(e + 1), w, ldc(e));
+          // A = C x_i = dt K N_j M_i, B = C x_j = A 2^(j-i)
+          const double A = (qj * K) * Mt.get(i);
+          const double Bm = ldexp(A, j - i);
+          const double Sm = A + Bm;
+          double F = 0.0;
+          if (has_flux) {
+            const double den = fmax(Mtj + Sm, DBL_MIN);
+            const double x1f = fmax(lnj1 - log(den), kX1Floor);
+            F = flux_fraction_f64(ldc(cj + i), x1f) * Sm;
+          }
+          L.set(i, L.get(i) + A);
+          // merged net of bin j: keeps Sm - F, loses Bm
+          const double cn = A - F;
+          netj += cn;
+          fout += F;
+          dneg += fmax(-cn, 0.0);
         }
-        L.set(i, L.get(i) + A);
-        const double cn = (Sm - F) - Bm;  // merged net of bin j, this pair
-        netj += cn;
-        fout += F;
-        dneg += fmax(-cn, 0.0);
+        // self pair: 2 x_j = x_{j+1} exactly, no flux; off grid for j = B-1
+        double self2 = 0.0;
+        if (j + 1 <= B - 1) {
+          const double *e = Kj + j * 2;
+          const double K = fma(ldc(e + 1), w, ldc(e));
+          const double A = 0.5 * ((qj * K) * Mtj);
+          self2 = A + A;
+        }
+        // S5 test: demand on bin j = its losses as the smaller partner (all
+        // rows above j are done) + self pair + negative merged nets here.
+        const double demand = L.get(j) + self2 + dneg;
+        flag = flag || (Mtj > 0.0 && demand > Mtj);
+        gj = 0.0 + (netj - self2);
+        if (j + 1 <= B - 1) g += fout + self2;
+        step_pairs += row_pairs<B>(act, j);
       }
-      // self pair: 2 x_j = x_{j+1} exactly, no flux; off grid for j = B-1
-      double self2 = 0.0;
-      if (j + 1 <= B - 1) {
-        const double *e = Kj + j * 2;
-        const double K = fma(ldc(e + 1), w, ldc(e));
-        const double A = 0.5 * ((qj * K) * Mtj);
-        self2 = A + A;
-      }
-      // S5 test: demand on bin j = its losses as the smaller partner (all
-      // rows above j are done) + self pair + negative merged nets here.
-      const double demand = L.get(j) + self2 + dneg;
-      flag = flag || (Mtj > 0.0 && demand > Mtj);
-      G[j * nthr] += netj - self2;
-      if (j + 1 <= B - 1) G[(j + 1) * nthr] += fout + self2;
-      step_pairs += row_pairs<B>(act, j);
+      if (j + 1 <= B - 1) finish(j + 1, g, Nj1);
+      g = gj;
+    }
+    if (uni) finish(lo, g, Nnext);
+    // bins outside [lo, hi+1] take no part in this step: carried over
+    if (live) {
+#pragma unroll 1
+      for (int k = 0; k < B; ++k)
+        if (!uni || k < lo || k > hi + 1)
+          so[k * kWave + lane] = sb[k * kWave + lane];
     }
 
     if (flag) {
       // the exact two-pass step (with the limiter) takes over this point
-      // for the rest of the launch
-      a.pending[slot] = a.nsteps - step;
+      // for the rest of the call; its state stays the one this step read,
+      // in both buffers
+      if (live) {
+#pragma unroll 1
+        for (int k = 0; k < B; ++k) so[k * kWave + lane] = sb[k * kWave + lane];
+      }
+      a.pending[slot] = a.steps_left - step;
       live = false;
     } else if (live) {
       npairs += step_pairs;
-      // reload the state rather than keep 2B registers live across the
-      // pair loop
-      asm volatile("" ::: "memory");
-      // S6: FP64 update, negative round-off clamped, back to numbers
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        double *q = sb + k * kWave + lane;
-        const double Mk = ldexp(__dmul_rn(*q, x1), k);
-        double Mn = Mk + (G[k * nthr] - L.get(k));
-        Mn = Mn < 0.0 ? 0.0 : Mn;
-        *q = ldexp(Mn / x1, -k);
-      }
     }
   }
   add_counters(a.counters, npairs);
 }
 
 // --------------------------------------------------------- FP32C kernel
+// Same sweep and double buffering as the FP64 kernel; the carried gain and
+// the losses are compensated FP32 sums, the update is FP64.
 template <int B, int WPB>
-__global__ void __launch_bounds__(kWave *WPB) lane_step_f32c(StepArgs a) {
+__global__ void __launch_bounds__(kWave *WPB)
+    __attribute__((amdgpu_waves_per_eu(B <= 33 ? 3 : 2))) lane_step_f32c(
+        StepArgs a) {
   constexpr int nthr = kWave * WPB;
-  __shared__ float lds_gf[2 * B * nthr];  // [s|c][bin][thread] gains
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int slot = blockIdx.x * nthr + tid;
@@ -224,22 +260,26 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f32c(StepArgs a) {
   const int wave_first = uniform(slot & ~(kWave - 1));
   if (wave_first >= nslots) return;
   const int br = wave_bracket(a.meta, wave_first, a.m.nbr);
-  bool live = slot < nslots && a.slot_point[slot] >= 0;
+  // a slot handed to the exact path earlier in the call stays there
+  bool live = slot < nslots && a.slot_point[slot] >= 0 && a.pending[slot] == 0;
   const double w = live ? a.wgt[slot] : 0.0;
   const float wf = (float)w;
   const float *__restrict__ Kf = a.m.KfT + (size_t)br * B * B * 2;
   const float *__restrict__ ctf = a.m.ctfT;
   const float *__restrict__ ixf = a.m.invxf;
   const double x1 = ldc(a.m.x);  // x_k = x_1 2^k exactly
-  double *const stw = a.state + (size_t)wave_first * B;
-  float *Gs = lds_gf + tid;
-  float *Gc = lds_gf + B * nthr + tid;
+  double *const stw0 = a.state + (size_t)wave_first * B;
+  double *const stw1 = a.state_alt + (size_t)wave_first * B;
   const double theta = a.m.theta, dt = a.dt;
   unsigned long long npairs = 0;
 
   for (int step = 0; step < a.nsteps; ++step) {
-    double *sb = stw;  // opaque per step, see the FP64 kernel
+    // this step reads one buffer and writes the other (opaque per step, see
+    // the FP64 kernel)
+    double *sb = (step & 1) ? stw1 : stw0;
+    double *so = (step & 1) ? stw0 : stw1;
     asm volatile("" : "+s"(sb));
+    asm volatile("" : "+s"(so));
     // S1/S2 in FP64; FP32 masses normalised by the FP64 total.
     double Mtot = 0.0;
 #pragma unroll
@@ -261,8 +301,6 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f32c(StepArgs a) {
       m.set(k, ak ? (float)(Mk * inv) : 0.0f);
       Ls.set(k, 0.0f);
       Lc.set(k, 0.0f);
-      Gs[k * nthr] = 0.0f;
-      Gc[k * nthr] = 0.0f;
     }
     const float tau = (float)(dt * Mtot);
     const uint64_t uni = wave_or64(act);
@@ -272,96 +310,116 @@ __global__ void __launch_bounds__(kWave *WPB) lane_step_f32c(StepArgs a) {
     const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
     bool flag = false;
     unsigned step_pairs = 0;
+    // S6 for bin k: FP64 update from the compensated gain (gs, gc) and the
+    // compensated losses, written to the other buffer
+    auto finish = [&](int k, float gs, float gc, double Nk) {
+      const double g = (double)gs + (double)gc;
+      const double l = (double)Ls.get(k) + (double)Lc.get(k);
+      const double Mk = ldexp(__dmul_rn(Nk, x1), k);
+      double Mn = Mk + (g - l) * Mtot;
+      Mn = Mn < 0.0 ? 0.0 : Mn;
+      if (live) so[k * kWave + lane] = ldexp(Mn / x1, -k);
+    };
+    // gain of bin j+1 from its own row, carried down one row
+    float gs = 0.0f, gc = 0.0f;
+    // state of bin j+1, loaded one row ahead of its update (rows run over
+    // the union [lo, hi] of the wave's active bins; bins lo..hi+1 change)
+    double Nnext = (hi + 1 <= B - 1) ? sb[(hi + 1) * kWave + lane] : 0.0;
 
     for (int j = hi; j >= lo; --j) {
-      if (!bit_of(uni_lo, uni_hi, j)) continue;
-      const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
-      const uint32_t cl = uni_lo & (uint32_t)below_mask;
-      const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
-      const float mj = m.get(j);
-      const float tj = (tau * mj) * ldc(ixf + j);  // A = K m_i tj
-      const bool has_flux = j <= B - 2;
-      const float lmj1 =
-          has_flux ? __builtin_amdgcn_logf(m.get(j + 1)) : 0.0f;  // log2
-      const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
-      const float *cj = ctf + (size_t)j * B;
-      float as = 0.0f, ac = 0.0f;  // mass arriving in bin j (compensated)
+      const double Nj1 = Nnext;
+      Nnext = sb[j * kWave + lane];
       float fs = 0.0f, fc = 0.0f;  // flux leaving bin j for j+1
+      float self2 = 0.0f;          // self-pair mass, bin j -> j+1
+      float ns = 0.0f, nc = 0.0f;  // gain of bin j from row j
+      if (bit_of(uni_lo, uni_hi, j)) {
+        const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+        const uint32_t cl = uni_lo & (uint32_t)below_mask;
+        const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
+        const float mj = m.get(j);
+        const float tj = (tau * mj) * ldc(ixf + j);  // A = K m_i tj
+        // the pressure weight folded into the row factor:
+        // tj K = tj K_{l+1} + (tj w) (K_l - K_{l+1})
+        const float tjw = tj * wf;
+        const bool has_flux = j <= B - 2;
+        const float lmj1 =
+            has_flux ? __builtin_amdgcn_logf(m.get(j + 1)) : 0.0f;  // log2
+        const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
+        const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, c ln 2)
+        float as = 0.0f, ac = 0.0f;  // mass arriving in bin j
 #pragma unroll
-      for (int i = 0; i < B - 1; ++i) {
-        if (!bit_of(cl, ch, i)) continue;
-        const float *e = Kj + i * 2;
-        const float K = __builtin_fmaf(ldc(e + 1), wf, ldc(e));
-        const float A = (tj * K) * m.get(i);
-        // x_j / x_i = 2^(j-i) exactly on the doubling grid
-        const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
-        const float Sm = A + Bm;
-        {
-          float s = Ls.get(i), c = Lc.get(i);
-          comp_add(s, c, A);
-          Ls.set(i, s);
-          Lc.set(i, c);
+        for (int i = 0; i < B - 1; ++i) {
+          if (!bit_of(cl, ch, i)) continue;
+          const float *e = Kj + i * 2;
+          const float tK = __builtin_fmaf(ldc(e + 1), tjw, tj * ldc(e));
+          const float A = tK * m.get(i);
+          // x_j / x_i = 2^(j-i) exactly on the doubling grid
+          const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
+          const float Sm = A + Bm;
+          {
+            float s = Ls.get(i), c = Lc.get(i);
+            comp_add_pos(s, c, A);
+            Ls.set(i, s);
+            Lc.set(i, c);
+          }
+          comp_add_pos(as, ac, A);
+          if (has_flux) {
+            const float den = __builtin_fmaxf(mj + Sm, 0x1p-120f);
+            float lam = lmj1 - __builtin_amdgcn_logf(den);
+            lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
+            const float c = ldc(cj + 2 * i), cl2 = ldc(cj + 2 * i + 1);
+            const float F = flux_fraction_f32(c, cl2, lam) * Sm;
+            comp_add_pos(fs, fc, F);
+          }
         }
-        comp_add(as, ac, A);
-        if (has_flux) {
-          const float den = __builtin_fmaxf(mj + Sm, 0x1p-120f);
-          float lam = lmj1 - __builtin_amdgcn_logf(den);
-          lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
-          const float c = ldc(cj + i);
-          const float F = flux_fraction_f32(c, c * kLn2f, lam) * Sm;
-          comp_add(fs, fc, F);
+        // self pair: transfer 2A from bin j to bin j+1 (exact hit, no flux)
+        if (j + 1 <= B - 1) {
+          const float *e = Kj + j * 2;
+          const float tK = __builtin_fmaf(ldc(e + 1), tjw, tj * ldc(e));
+          const float A = 0.5f * (tK * mj);
+          self2 = A + A;
+        }
+        // S5 bound: losses as the smaller partner + self pair + every flux
+        // leaving bin j (>= the negative merged nets); FP32 margin.
+        const float demand = (Ls.get(j) + Lc.get(j)) + self2 + (fs + fc);
+        flag = flag || (mj > 0.0f && demand > mj * (1.0f - 1e-5f));
+        comp_add(ns, nc, as);
+        comp_add(ns, nc, ac);
+        comp_add(ns, nc, -fs);
+        comp_add(ns, nc, -fc);
+        comp_add(ns, nc, -self2);
+        step_pairs += row_pairs<B>(act, j);
+        if (j + 1 <= B - 1) {
+          comp_add(gs, gc, fs);
+          comp_add(gs, gc, fc);
+          comp_add(gs, gc, self2);
         }
       }
-      // self pair: transfer 2A from bin j to bin j+1 (exact hit, no flux)
-      float self2 = 0.0f;
-      if (j + 1 <= B - 1) {
-        const float *e = Kj + j * 2;
-        const float K = __builtin_fmaf(ldc(e + 1), wf, ldc(e));
-        const float A = 0.5f * ((tj * K) * mj);
-        self2 = A + A;
-      }
-      // S5 bound: losses as the smaller partner + self pair + every flux
-      // leaving bin j (>= the negative merged nets); FP32 margin.
-      const float demand = (Ls.get(j) + Lc.get(j)) + self2 + (fs + fc);
-      flag = flag || (mj > 0.0f && demand > mj * (1.0f - 1e-5f));
-      {
-        float s = Gs[j * nthr], c = Gc[j * nthr];
-        comp_add(s, c, as);
-        comp_add(s, c, ac);
-        comp_add(s, c, -fs);
-        comp_add(s, c, -fc);
-        comp_add(s, c, -self2);
-        Gs[j * nthr] = s;
-        Gc[j * nthr] = c;
-      }
-      if (j + 1 <= B - 1) {
-        float s = Gs[(j + 1) * nthr], c = Gc[(j + 1) * nthr];
-        comp_add(s, c, fs);
-        comp_add(s, c, fc);
-        comp_add(s, c, self2);
-        Gs[(j + 1) * nthr] = s;
-        Gc[(j + 1) * nthr] = c;
-      }
-      step_pairs += row_pairs<B>(act, j);
+      if (j + 1 <= B - 1) finish(j + 1, gs, gc, Nj1);
+      gs = ns;
+      gc = nc;
+    }
+    if (uni) finish(lo, gs, gc, Nnext);
+    // bins outside [lo, hi+1] take no part in this step: carried over
+    if (live) {
+#pragma unroll 1
+      for (int k = 0; k < B; ++k)
+        if (!uni || k < lo || k > hi + 1)
+          so[k * kWave + lane] = sb[k * kWave + lane];
     }
 
     if (flag) {
-      a.pending[slot] = a.nsteps - step;
+      // the exact two-pass step (with the limiter) takes over this point
+      // for the rest of the call; its state stays the one this step read,
+      // in both buffers
+      if (live) {
+#pragma unroll 1
+        for (int k = 0; k < B; ++k) so[k * kWave + lane] = sb[k * kWave + lane];
+      }
+      a.pending[slot] = a.steps_left - step;
       live = false;
     } else if (live) {
       npairs += step_pairs;
-      asm volatile("" ::: "memory");
-      // FP64 update from the compensated FP32 sums (exact sum = s + c)
-#pragma unroll
-      for (int k = 0; k < B; ++k) {
-        const double g = (double)Gs[k * nthr] + (double)Gc[k * nthr];
-        const double l = (double)Ls.get(k) + (double)Lc.get(k);
-        double *q = sb + k * kWave + lane;
-        const double Mk = ldexp(__dmul_rn(*q, x1), k);
-        double Mn = Mk + (g - l) * Mtot;
-        Mn = Mn < 0.0 ? 0.0 : Mn;
-        *q = ldexp(Mn / x1, -k);
-      }
     }
   }
   add_counters(a.counters, npairs);

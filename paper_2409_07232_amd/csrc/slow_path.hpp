@@ -59,23 +59,37 @@ __device__ __forceinline__ bool pair_nets_f64(const DevModel &m,
     if (!(x1 >= kX1Floor)) x1 = kX1Floor;
     F = flux_fraction_f64(m.ct[i * B + j], x1) * Sm;
   }
-  out.put(a * B + i, -A);
-  out.put(b * B + j, -Bm);
-  out.put(P * B + k, Sm - F);
-  if (k <= B - 2) out.put(P * B + k + 1, F);
+  // a source bin that also receives the merged mass gets the other
+  // source's collided mass minus the flux in one subtraction (no rounded
+  // A + Bm followed by the removal of Bm)
+  const int qa = a * B + i, qb = b * B + j, qk = P * B + k;
+  if (qk == qb && qk != qa) {
+    out.put(qa, -A);
+    out.put(qb, A - F);
+  } else if (qk == qa && qk != qb) {
+    out.put(qa, Bm - F);
+    out.put(qb, -Bm);
+  } else {
+    out.put(qa, -A);
+    out.put(qb, -Bm);
+    out.put(qk, Sm - F);
+  }
+  if (k <= B - 2) out.put(qk + 1, F);
   return true;
 }
 
 // One FP64 step of the point whose bins sit at st[q * stride], q =
-// species*B + bin.  Returns 1 if the limiter fired.  *npairs counts evaluated pairs.
-template <int MAXSB>
-__device__ __noinline__ int slow_step_f64(const DevModel &m, double *st,
-                                          int stride, double w, int br,
-                                          double dt,
-                                          unsigned long long *npairs) {
+// species*B + bin, in the oracle's two-pass structure.  work holds 7 arrays
+// of S*B doubles (private memory or global scratch).  Returns 1 if the
+// limiter fired; *npairs counts evaluated pairs.
+__device__ __noinline__ int slow_step_core(const DevModel &m, double *st,
+                                           int stride, double w, int br,
+                                           double dt,
+                                           unsigned long long *npairs,
+                                           double *work) {
   const int B = m.B, S = m.S, n = S * B;
-  double M[MAXSB], Mt[MAXSB], Nv[MAXSB], G[MAXSB], L[MAXSB], D[MAXSB],
-      sig[MAXSB];
+  double *M = work, *Mt = work + n, *Nv = work + 2 * n, *G = work + 3 * n,
+         *L = work + 4 * n, *D = work + 5 * n, *sig = work + 6 * n;
   double Mtot = 0.0;
   for (int q = 0; q < n; ++q) {
     Nv[q] = st[(size_t)q * stride];
@@ -138,6 +152,16 @@ __device__ __noinline__ int slow_step_f64(const DevModel &m, double *st,
   }
   *npairs += cnt;
   return limited;
+}
+
+// Same with private arrays for up to MAXSB bins.
+template <int MAXSB>
+__device__ __forceinline__ int slow_step_f64(const DevModel &m, double *st,
+                                             int stride, double w, int br,
+                                             double dt,
+                                             unsigned long long *npairs) {
+  double work[7 * MAXSB];
+  return slow_step_core(m, st, stride, w, br, dt, npairs, work);
 }
 
 }  // namespace fsbm

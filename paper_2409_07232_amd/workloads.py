@@ -32,10 +32,17 @@ P_LEVELS_3 = np.array([1000.0, 750.0, 500.0])
 SPECIES_4 = ("liquid", "ice", "snow", "graupel")
 BETA_4 = (0.8, 0.3, 0.4, 0.6)
 RHO_4 = (1.0, 0.9, 0.1, 0.4)
-# product species of a collision, symmetric: l+l->l, i+i->s, s+s->s,
-# g+g->g, l+i->g, l+s->s, l+g->g, i+s->s, i+g->g, s+g->g
-PRODUCT_4 = np.array([[0, 3, 2, 3],
-                      [3, 2, 2, 3],
+# Initial spectra per species: gamma mean radius (cm) and the log-uniform
+# range of the species content (g/m^3).  Ice species are fewer and larger
+# than cloud drops, so per-bin collection rates stay below one per 2 s step
+# at almost every point (the positivity limiter is the exception).
+RBAR_4 = (10.0e-4, 100.0e-4, 300.0e-4, 500.0e-4)
+CONTENT_4 = ((0.1, 3.0), (0.01, 0.3), (0.01, 0.5), (0.01, 1.0))
+# product species of a collision, symmetric: riming keeps the collector's
+# ice species (l+i->i, l+s->s, l+g->g), aggregation of crystals and snow
+# gives snow (i+i->s, i+s->s, s+s->s), anything with graupel stays graupel.
+PRODUCT_4 = np.array([[0, 1, 2, 3],
+                      [1, 2, 2, 3],
                       [2, 2, 2, 3],
                       [3, 3, 3, 3]], dtype=np.int32)
 # Config-4 species: liquid and graupel.
@@ -134,8 +141,10 @@ def liquid_tables(nbins, s=1, p_levels=P_LEVELS_3):
 
 
 def multi_species_vcoef(beta):
-    # every species falls at the same speed at r = 100 um
-    return tuple(8.0e3 * 0.01 ** (0.8 - b) for b in beta)
+    # every species falls at the speed of the smallest drop (r = 2 um) at
+    # that radius; above it, the smaller exponents of the ice species make
+    # them fall slower than drops of the same radius
+    return tuple(8.0e3 * R1_CM ** (0.8 - b) for b in beta)
 
 
 def gamma_spectrum_masses(x, rho, nu, rbar_cm, mtot):
@@ -221,9 +230,11 @@ def config2(nx: int = 256, ny: int = 256, nz: int = 50, nsteps: int = 100,
 
 
 # ---------------------------------------------------------------- config 3
-def _multi_species_states(rng, x, rho, present, npoints, window):
-    """Per species: gamma spectrum with its own content; optional random
-    active window [lo, hi] outside which the spectrum is zeroed."""
+def _multi_species_states(rng, x, rho, rbar, content_rng, present, npoints,
+                          window):
+    """Per species: gamma spectrum with its own mean radius and content;
+    optional random active window [lo, hi] outside which the spectrum is
+    zeroed (the content inside the window is kept as drawn)."""
     S = len(rho)
     B = x.size
     N = np.zeros((npoints, S, B))
@@ -231,16 +242,13 @@ def _multi_species_states(rng, x, rho, present, npoints, window):
         sel = np.flatnonzero(present[:, a])
         n = sel.size
         nu = rng.uniform(2.0, 6.0, n)
-        content = _log_uniform(rng, 0.1, 3.0, n)
-        M = gamma_spectrum_masses(x, rho[a], nu, 1.0e-3, content * 1e-6)
+        content = _log_uniform(rng, content_rng[a][0], content_rng[a][1], n)
+        M = gamma_spectrum_masses(x, rho[a], nu, rbar[a], content * 1e-6)
         if window is not None:
             lo = rng.integers(window[0][0], window[0][1] + 1, n)
             hi = rng.integers(window[1][0], window[1][1] + 1, n)
             kk = np.arange(B)[None, :]
             M = np.where((kk >= lo[:, None]) & (kk <= hi[:, None]), M, 0.0)
-            # keep the species' content after windowing
-            tot = M.sum(axis=1, keepdims=True)
-            M *= (content[:, None] * 1e-6) / np.where(tot > 0, tot, 1.0)
         N[sel, a, :] = M / x[None, :]
     return N
 
@@ -255,7 +263,8 @@ def config3(npoints: int = 1 << 20, nsteps: int = 100,
     present = np.ones((npoints, S), dtype=bool)
     present[:, 1:] = rng.random((npoints, 3)) < 0.3
     window = ((0, 5), (15, 32))
-    N = _multi_species_states(rng, x, RHO_4, present, npoints, window)
+    N = _multi_species_states(rng, x, RHO_4, RBAR_4, CONTENT_4, present,
+                              npoints, window)
     p = rng.uniform(500.0, 1000.0, npoints)
     tables = gravitational_tables(B, 1, RHO_4, BETA_4,
                                   multi_species_vcoef(BETA_4), P_LEVELS_3)
@@ -265,16 +274,24 @@ def config3(npoints: int = 1 << 20, nsteps: int = 100,
 
 
 # ---------------------------------------------------------------- config 4
+def _liquid_graupel():
+    """Densities, exponents, mean radii and content ranges of the two
+    species of the refined grids."""
+    pick = (0, 3)
+    return (tuple(RHO_4[a] for a in pick), tuple(BETA_4[a] for a in pick),
+            tuple(RBAR_4[a] for a in pick), tuple(CONTENT_4[a] for a in pick))
+
+
 def config4(nbins: int = 66, npoints: int = 262144, nsteps: int = 100,
             dt: float = 2.0, config_id: int = 4) -> Workload:
     """Liquid + graupel on a refined grid (66/132/264 bins, s = 2/4/8)."""
     s = {66: 2, 132: 4, 264: 8}[nbins]
     rng = rng_for(config_id)
-    rho = (RHO_4[0], RHO_4[3])
-    beta = (BETA_4[0], BETA_4[3])
+    rho, beta, rbar, cont = _liquid_graupel()
     x = bin_masses(nbins, s)
     present = np.ones((npoints, 2), dtype=bool)
-    N = _multi_species_states(rng, x, rho, present, npoints, None)
+    N = _multi_species_states(rng, x, rho, rbar, cont, present, npoints,
+                              None)
     p = rng.uniform(500.0, 1000.0, npoints)
     tables = gravitational_tables(nbins, s, rho, beta,
                                   multi_species_vcoef(beta), P_LEVELS_3)
@@ -300,17 +317,18 @@ def config5(npoints: int = 1 << 22, nsteps: int = 100, dt: float = 2.0,
         cl = cloudy[sel]
         if S == 4:
             rho, beta, prod = RHO_4, BETA_4, PRODUCT_4
+            rbar, cont = RBAR_4, CONTENT_4
             present = np.zeros((n, S), dtype=bool)
             present[:, 0] = cl
             present[:, 1:] = (rng.random((n, 3)) < 0.3) & cl[:, None]
             window = ((0, 5), (15, 32))
         else:
-            rho = (RHO_4[0], RHO_4[3])
-            beta = (BETA_4[0], BETA_4[3])
+            rho, beta, rbar, cont = _liquid_graupel()
             prod = PRODUCT_2
             present = np.repeat(cl[:, None], 2, axis=1)
             window = None
-        N = _multi_species_states(rng, x, rho, present, n, window)
+        N = _multi_species_states(rng, x, rho, rbar, cont, present, n,
+                                  window)
         p = rng.uniform(500.0, 1000.0, n)
         tables = gravitational_tables(B, s, rho, beta,
                                       multi_species_vcoef(beta), P_LEVELS_3)

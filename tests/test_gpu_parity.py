@@ -8,26 +8,17 @@ drift 1e-10 for both.
 import numpy as np
 import pytest
 
-import oracle
-from oracle import compare
 from paper_2409_07232_amd import workloads as wl
+from tests.parity import DRIFT, check, run_oracle
 
 torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 1: 1e-5}
-DRIFT = 1e-10
-
 
 def _lib():
     from paper_2409_07232_amd import _lib as L
     return L
-
-
-def model_of(w):
-    return oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
-                              w.product, x1_g=w.x1_g, s=w.s, theta=w.theta)
 
 
 def run_gpu(w, precision, N=None, p=None, dt=None, nsteps=None, flags=0,
@@ -47,31 +38,14 @@ def run_gpu(w, precision, N=None, p=None, dt=None, nsteps=None, flags=0,
     return out, st, h
 
 
-def run_oracle(w, N=None, p=None, dt=None, nsteps=None):
-    om = model_of(w)
-    Nr = np.array(w.N if N is None else N, dtype=np.float64, copy=True)
-    om.run(Nr, w.p if p is None else p, w.dt if dt is None else dt,
-           w.nsteps if nsteps is None else nsteps)
-    return Nr, om.grid()
-
-
-def check(got, ref, start, x, precision, label="", floor=1e-9):
-    err = compare.rel_bin(got, ref, x, floor=floor)
-    drift = compare.drift(got, start, x)
-    print("%s precision=%d rel_bin=%.3e drift=%.3e" % (label, precision, err,
-                                                      drift), flush=True)
-    assert np.all(got >= 0.0)
-    assert err <= TOL[precision], err
-    assert drift <= DRIFT, drift
-
-
 @pytest.mark.parametrize("precision", [0, 1])
 def test_golovin_full_run(precision):
     """64 identical points, 33 bins, Golovin kernel, dt 1 s x 1800 steps."""
     w = wl.config1(npoints=64)
-    ref, x = run_oracle(w.subset(np.arange(1)))
+    ref, x, lim = run_oracle(w.subset(np.arange(1)))
     got, st, _ = run_gpu(w, precision)
-    check(got, np.repeat(ref, 64, axis=0), w.N, x, precision, "golovin")
+    check(got, np.repeat(ref, 64, axis=0), w.N, x, precision, "golovin",
+          limited=np.repeat(lim, 64))
     assert st["active_points"] == 64
     assert st["limiter_steps"] == 0
 
@@ -81,11 +55,11 @@ def test_thunderstorm_patch_small(precision):
     """Config-2 recipe on a 16 x 16 x 50 patch (about 1900 cloudy points,
     several waves per pressure bracket and ragged tails), 100 steps."""
     w = wl.config2(nx=16, ny=16, nz=50)
-    ref, x = run_oracle(w)
+    ref, x, lim = run_oracle(w)
     got, st, _ = run_gpu(w, precision)
     dry = ~w.cloudy()
     assert np.array_equal(got[dry], w.N[dry])
-    check(got, ref, w.N, x, precision, "patch16")
+    check(got, ref, w.N, x, precision, "patch16", limited=lim)
     assert st["active_points"] == int((~dry).sum())
 
 
@@ -97,9 +71,9 @@ def test_ragged_point_counts(precision, npts):
                                                      replace=False))
     sub = w.subset(idx)
     sub.nsteps = 20
-    ref, x = run_oracle(sub)
+    ref, x, lim = run_oracle(sub)
     got, _, _ = run_gpu(sub, precision)
-    check(got, ref, sub.N, x, precision, "ragged%d" % npts)
+    check(got, ref, sub.N, x, precision, "ragged%d" % npts, limited=lim)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -130,16 +104,14 @@ def test_degenerate_calls(precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_forced_limiter(precision):
     """A huge time step over-demands bins: the limiter path must match the
-    oracle and keep mass and positivity.  The limiter empties an
-    over-demanded bin by the exact cancellation M - (M / D) D, so what is left
-    there is rounding noise of order u M; bins below 1e-6 of their point's
-    mass are therefore judged on that absolute scale here."""
+    oracle and keep mass and positivity (limited points are judged with the
+    limiter floor of the parity helpers)."""
     w = wl.config2(nx=8, ny=8, nz=50)
     sub = w.subset(wl.sample_active(w, 96))
-    ref, x = run_oracle(sub, dt=4000.0, nsteps=3)
+    ref, x, lim = run_oracle(sub, dt=4000.0, nsteps=3)
     got, st, _ = run_gpu(sub, precision, dt=4000.0, nsteps=3)
-    assert st["limiter_steps"] > 0
-    check(got, ref, sub.N, x, precision, "limiter", floor=1e-6)
+    assert st["limiter_steps"] > 0 and lim.sum() > 0
+    check(got, ref, sub.N, x, precision, "limiter", limited=lim)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -211,7 +183,7 @@ def test_full_size_thunderstorm_sampled(precision):
     got = N[torch.from_numpy(idx).to("cuda")].cpu().numpy()
     assert np.all(got >= 0)
     sub = w.subset(idx)
-    ref, x = run_oracle(sub)
-    check(got, ref, sub.N, x, precision, "full-sampled")
+    ref, x, lim = run_oracle(sub)
+    check(got, ref, sub.N, x, precision, "full-sampled", limited=lim)
     st = h.stats()
     assert st["active_points"] == int(cl.sum())
