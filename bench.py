@@ -40,6 +40,20 @@ FLOPS_PER_PAIR = 29
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 
+# HBM bytes per launch of a kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by the same counters on a 1 GiB device copy (the profile
+# summary under profiles/ gives the commands).  They hold only for the
+# kernel sources they were taken on: the SHA-256 of the concatenated files
+# below must match, otherwise the traffic entry is reported as null.
+TRAFFIC_SOURCES = ("kernels_lane.hip", "device_common.hpp",
+                   "fsbm_internal.hpp")
+MEASURED_TRAFFIC = {
+    # kernel: (sources sha256, bytes per launch, profile summary)
+    "lane_step_f32c<33>": (
+        "afd8c241a12064f84ef7d1da8c7151172bfaec9158e24cd77cfe9d352f0ac2aa",
+        3.753e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -52,6 +66,9 @@ def parse():
     ap.add_argument("--workload", default="thunderstorm",
                     choices=["thunderstorm", "four_species", "refined66",
                              "refined132", "refined264", "mixed"])
+    ap.add_argument("--points", type=int, default=0,
+                    help="point count of the four_species, refined and "
+                         "mixed workloads (default: the configuration's)")
     ap.add_argument("--collision-steps", type=int, default=0,
                     help="collision steps per call (default: the "
                          "workload's 100)")
@@ -83,17 +100,20 @@ def time_calls(run_once, handles, steps, warmup, nsteps):
     """Warm up, then time `steps` calls of run_once(); the first handle
     holds the launch timings and pair counters of a multi-grid call."""
     import torch
-    for _ in range(warmup):
+    for k in range(warmup):
         run_once()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("warm-up call %d done" % (k + 1))
     st0 = [h.stats() for h in handles]
     pairs = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         run_once()
         sts = [h.stats() for h in handles]   # synchronises the stream
         pairs += sum(st["pair_evals"] for st in sts)
+        log("timed call %d done, %.1f s so far" % (k + 1,
+                                                  time.perf_counter() - t0))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = [h.stats() for h in handles]
@@ -145,12 +165,26 @@ def time_multi(ws, precision, steps, warmup, N0s, ps, batched):
     return r
 
 
-def roofline(res, peak):
+def measured_traffic(kernel):
+    """Profiled HBM bytes per launch, or None if the kernel changed."""
+    import hashlib
+    entry = MEASURED_TRAFFIC.get(kernel)
+    if entry is None:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_07232_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return entry[1] if h.hexdigest() == entry[0] else None
+
+
+def roofline(res, peak, kernel=None):
     achieved = FLOPS_PER_PAIR * res["pair_evals"] / (res["kernel_ms"] * 1e-3)
     achieved /= 1e12
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-            "traffic": None}
+            "traffic": measured_traffic(kernel) if kernel else None}
 
 
 def _oracle_model(w):
@@ -243,18 +277,20 @@ def make_workloads(args):
                    args.nx, args.ny, args.nz),
                "kernel_tables": "gravitational, 3 pressure levels"}
     elif name == "four_species":
-        ws = [wl.config3()]
-        cfg = {"workload": "four_species_2^20pts_33bins",
+        ws = [wl.config3(npoints=args.points or (1 << 20))]
+        cfg = {"workload": "four_species_%dpts_33bins" % ws[0].npoints,
                "kernel_tables": "10 gravitational pair tables, 3 levels"}
     elif name.startswith("refined"):
         nb = int(name[len("refined"):])
-        ws = [wl.config4(nbins=nb)]
-        cfg = {"workload": "liquid_graupel_262144pts_%dbins" % nb,
+        ws = [wl.config4(nbins=nb, npoints=args.points or 262144)]
+        cfg = {"workload": "liquid_graupel_%dpts_%dbins" % (ws[0].npoints,
+                                                             nb),
                "kernel_tables": "3 gravitational pair tables, 3 levels"}
     else:
-        ws = wl.config5()
+        ws = wl.config5(npoints=args.points or (1 << 22))
         ws.sort(key=lambda w: -w.nspecies * w.nbins)
-        cfg = {"workload": "mixed_grids_2^22pts_10pct_cloudy_33_66_132bins",
+        cfg = {"workload": "mixed_grids_%dpts_10pct_cloudy_33_66_132bins" %
+                           sum(w.npoints for w in ws),
                "kernel_tables": "per grid, 3 levels"}
     if args.collision_steps:
         for w in ws:
@@ -342,7 +378,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": cfg,
-        "roofline": roofline(r32, PEAK_FP32_TFLOPS),
+        "roofline": roofline(r32, PEAK_FP32_TFLOPS,
+                             kernel_name(r32["stats"], 1, w0.nbins)),
         "kernel": {"name": kernel_name(r32["stats"], 1, w0.nbins),
                    "avg_launch_ms": round(r32["kernel_avg_ms"], 4),
                    "launches": r32["kernel_launches"],

@@ -148,10 +148,15 @@ typedef struct {
                              mass inside the grid), summed over points and
                              steps of the last call */
   int64_t limiter_steps;  /* point-steps where the positivity limiter ran */
-  int64_t fp64_fallback_steps; /* point-steps taken on the exact FP64 path:
-                                  once a point's fast kernel finds that the
-                                  limiter may fire, the point takes every
-                                  remaining step of the call there */
+  int64_t fp64_fallback_steps; /* point-steps taken in FP64 outside the
+                                  fast path: one point per lane, once the
+                                  fast kernel finds that the limiter may
+                                  fire, the point takes every remaining step
+                                  of the call on the exact FP64 path; one
+                                  point per wave in FP32C mode, once the
+                                  limiter fires the point takes that and
+                                  every remaining step of the call in FP64
+                                  mode */
   int32_t kernel;         /* 0 = one point per lane, 1 = one point per wave */
   int32_t steps_per_launch;
   int32_t waves_per_block;

@@ -112,11 +112,21 @@ __device__ __forceinline__ void comp_add(float &s, float &c, float x) {
 // The same for a non-negative running sum and a non-negative term: with
 // the larger operand first, Dekker's Fast2Sum recovers the same exact
 // rounding error as TwoSum (identical s and c) in one operation less.
+__device__ __forceinline__ float vmax_f32(float a, float b) {
+  // plain v_max_f32: both operands are finite, so the NaN quieting the
+  // compiler adds around fmaxf is not needed
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmin_f32(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 __device__ __forceinline__ void comp_add_pos(float &s, float &c, float x) {
-  // max and min as three-operand medians (no NaN canonicalisation needed:
-  // both operands are finite)
-  const float a = __builtin_amdgcn_fmed3f(s, x, __builtin_inff());
-  const float b = __builtin_amdgcn_fmed3f(s, x, -__builtin_inff());
+  const float a = vmax_f32(s, x);
+  const float b = vmin_f32(s, x);
   const float t = a + b;
   const float e = b - (t - a);
   c += e;

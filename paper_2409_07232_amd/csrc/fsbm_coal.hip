@@ -66,7 +66,6 @@ struct fsbm_coal_s {
   void *wmem = nullptr;
   int64_t wpoints = -1;  // points the workspace was laid out for
   DevWork ws{};
-  double *scratch = nullptr;  // exact path of the wave kernel
   int nblocks = 0;
   // graph cache
   hipGraph_t graph = nullptr;
@@ -146,12 +145,32 @@ void write_tune_cache(fsbm_coal_t h) {
 // merged mass lands in it (canonical order), for every bin the pairs it
 // loses mass in (transfers that stay in the bin are left out), and a
 // load-balanced assignment of bins to the 64 lanes.
-int build_wave_tables(fsbm_coal_t h, std::vector<short> &own,
-                      std::vector<int> &tgt_off, std::vector<unsigned> &tgt,
-                      std::vector<int> &loss_off,
-                      std::vector<unsigned> &loss) {
+// Tables of the one-point-per-wave kernel: bin ownership and the per-lane
+// gain and loss streams (see DevModel).
+struct WaveTables {
+  std::vector<short> own;
+  int rows_g = 0, rows_l = 0;
+  std::vector<uint2> idx;
+  std::vector<float2> x32, c32, k32;
+  std::vector<double2> x64, k64;
+  std::vector<double> c64;
+};
+
+int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
+                      const std::vector<float> &Kf,
+                      const std::vector<float> &xf,
+                      const std::vector<float> &ctf, int nbr,
+                      WaveTables &wt) {
   const int B = h->B, S = h->S, SB = S * B;
-  std::vector<std::vector<unsigned>> T(SB), Lq(SB);
+  if (SB > kWave * kMaxOwn) return FSBM_EUNSUPPORTED;
+  struct Pair {
+    int a, i, b, j;
+    bool sideb;
+  };
+  // pairs landing in each bin, and pairs each bin loses mass to (a bin that
+  // is also the pair's target has no separate loss: its merged net is
+  // formed on the gain side)
+  std::vector<std::vector<Pair>> T(SB), Lq(SB);
   for (int a = 0; a < S; ++a)
     for (int b = a; b < S; ++b)
       for (int i = 0; i < B; ++i)
@@ -160,32 +179,16 @@ int build_wave_tables(fsbm_coal_t h, std::vector<short> &own,
           if (k < 0) continue;
           const int P = h->product[(size_t)a * S + b];
           const int qt = P * B + k, qa = a * B + i, qb = b * B + j;
-          const unsigned e = pack_pair(a, i, b, j);
-          const unsigned et =
-              e | (qa == qt ? kEntTA : 0u) | (qb == qt ? kEntTB : 0u);
-          T[qt].push_back(et);
+          T[qt].push_back({a, i, b, j, false});
           if (qa == qb) {
-            Lq[qa].push_back(e | kEntSelf);
+            Lq[qa].push_back({a, i, b, j, false});
           } else {
-            if (qa != qt) Lq[qa].push_back(e);
-            if (qb != qt) Lq[qb].push_back(e | kEntSideB);
+            if (qa != qt) Lq[qa].push_back({a, i, b, j, false});
+            if (qb != qt) Lq[qb].push_back({a, i, b, j, true});
           }
         }
-  tgt_off.assign(SB + 1, 0);
-  loss_off.assign(SB + 1, 0);
-  tgt.clear();
-  loss.clear();
-  for (int q = 0; q < SB; ++q) {
-    tgt_off[q] = (int)tgt.size();
-    tgt.insert(tgt.end(), T[q].begin(), T[q].end());
-    loss_off[q] = (int)loss.size();
-    loss.insert(loss.end(), Lq[q].begin(), Lq[q].end());
-  }
-  tgt_off[SB] = (int)tgt.size();
-  loss_off[SB] = (int)loss.size();
-  // longest-processing-time assignment; a target entry costs about four
-  // loss entries
-  if (SB > kWave * kMaxOwn) return FSBM_EUNSUPPORTED;
+  // longest-processing-time assignment of bins to lanes; a gain entry costs
+  // about four loss entries
   std::vector<int> order(SB);
   std::vector<double> wgt(SB);
   for (int q = 0; q < SB; ++q) {
@@ -193,16 +196,71 @@ int build_wave_tables(fsbm_coal_t h, std::vector<short> &own,
     wgt[q] = 4.0 * T[q].size() + Lq[q].size() + 1.0;
   }
   std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return wgt[a] > wgt[b]; });
+                   [&](int x, int y) { return wgt[x] > wgt[y]; });
   std::vector<double> load(kWave, 0.0);
   std::vector<int> cnt(kWave, 0);
-  own.assign((size_t)kWave * kMaxOwn, (short)-1);
+  wt.own.assign((size_t)kWave * kMaxOwn, (short)-1);
   for (int q : order) {
     int best = -1;
     for (int l = 0; l < kWave; ++l)
       if (cnt[l] < kMaxOwn && (best < 0 || load[l] < load[best])) best = l;
-    own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
+    wt.own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
     load[best] += wgt[q];
+  }
+  // stream lengths per lane
+  std::vector<int> len_g(kWave, 0), len_l(kWave, 0);
+  for (int l = 0; l < kWave; ++l)
+    for (int o = 0; o < kMaxOwn; ++o) {
+      const int q = wt.own[(size_t)l * kMaxOwn + o];
+      if (q < 0) continue;
+      len_g[l] += (int)T[q].size();
+      len_l[l] += (int)Lq[q].size();
+    }
+  wt.rows_g = *std::max_element(len_g.begin(), len_g.end());
+  wt.rows_l = *std::max_element(len_l.begin(), len_l.end());
+  const size_t n = (size_t)(wt.rows_g + wt.rows_l) * kWave;
+  wt.idx.assign(n, make_uint2(0u, 0u));
+  wt.x32.assign(n, make_float2(0.f, 0.f));
+  wt.c32.assign(n, make_float2(0.f, 0.f));
+  wt.x64.assign(n, make_double2(0.0, 0.0));
+  wt.c64.assign(n, 0.0);
+  wt.k32.assign(n * nbr, make_float2(0.f, 0.f));
+  wt.k64.assign(n * nbr, make_double2(0.0, 0.0));
+  auto put = [&](size_t pos, const Pair &pr, bool loss_side) {
+    const int k = h->kt[(size_t)pr.i * B + pr.j];
+    const int P = h->product[(size_t)pr.a * S + pr.b];
+    const int qt = P * B + k, qa = pr.a * B + pr.i, qb = pr.b * B + pr.j;
+    unsigned fl = kWValid;
+    if (qa == qt) fl |= kWTA;
+    if (qb == qt) fl |= kWTB;
+    if (qa == qb) fl |= kWSelf;
+    if (loss_side && pr.sideb) fl |= kWSideB;
+    if (k <= B - 2) fl |= kWFlux;
+    wt.idx[pos] = make_uint2((unsigned)qa | ((unsigned)qb << 16),
+                             (unsigned)qt | (fl << 16));
+    wt.x32[pos] = make_float2(xf[pr.i], xf[pr.j]);
+    wt.x64[pos] = make_double2(h->x[pr.i], h->x[pr.j]);
+    const size_t ij = (size_t)pr.i * B + pr.j;
+    // FP32 Courant number and its product with ln 2 as the kernels round it
+    wt.c32[pos] = make_float2(ctf[ij], ctf[ij] * kLn2f);
+    wt.c64[pos] = h->ct[ij];
+    const int ab = pr.a * S - (pr.a * (pr.a - 1)) / 2 + (pr.b - pr.a);
+    for (int br = 0; br < nbr; ++br) {
+      const size_t t = (((size_t)ab * nbr + br) * B * B + ij) * 2;
+      wt.k32[(size_t)br * n + pos] = make_float2(Kf[t], Kf[t + 1]);
+      wt.k64[(size_t)br * n + pos] = make_double2(Kd[t], Kd[t + 1]);
+    }
+  };
+  for (int l = 0; l < kWave; ++l) {
+    int rg = 0, rl = 0;
+    for (int o = 0; o < kMaxOwn; ++o) {
+      const int q = wt.own[(size_t)l * kMaxOwn + o];
+      if (q < 0) continue;
+      for (const Pair &pr : T[q])
+        put((size_t)(rg++) * kWave + l, pr, false);
+      for (const Pair &pr : Lq[q])
+        put((size_t)(wt.rows_g + rl++) * kWave + l, pr, true);
+    }
   }
   return FSBM_OK;
 }
@@ -282,11 +340,9 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       ctfT[((size_t)j * B + i) * 2] = cf;
       ctfT[((size_t)j * B + i) * 2 + 1] = cf * kLn2f;
     }
-  std::vector<short> own;
-  std::vector<int> tgt_off, loss_off;
-  std::vector<unsigned> tgt, loss;
+  WaveTables wt;
   const bool wave_ok = S * B <= kWave * kMaxOwn;
-  if (wave_ok) RC_TRY(build_wave_tables(h, own, tgt_off, tgt, loss_off, loss));
+  if (wave_ok) RC_TRY(build_wave_tables(h, Kd, Kf, xf, ctf, nbr, wt));
   if (!h->lane && !wave_ok) return FSBM_EUNSUPPORTED;
   struct Part {
     const void *src;
@@ -309,11 +365,14 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       {KfT.data(), sizeof(float) * nT, 0},
       {ctfT.data(), sizeof(float) * B * B * 2, 0},
       {xf.data(), sizeof(float) * B, 0},
-      {own.data(), sizeof(short) * own.size(), 0},
-      {tgt_off.data(), sizeof(int) * tgt_off.size(), 0},
-      {tgt.data(), sizeof(unsigned) * tgt.size(), 0},
-      {loss_off.data(), sizeof(int) * loss_off.size(), 0},
-      {loss.data(), sizeof(unsigned) * loss.size(), 0},
+      {wt.own.data(), sizeof(short) * wt.own.size(), 0},
+      {wt.idx.data(), sizeof(uint2) * wt.idx.size(), 0},
+      {wt.x32.data(), sizeof(float2) * wt.x32.size(), 0},
+      {wt.x64.data(), sizeof(double2) * wt.x64.size(), 0},
+      {wt.c32.data(), sizeof(float2) * wt.c32.size(), 0},
+      {wt.c64.data(), sizeof(double) * wt.c64.size(), 0},
+      {wt.k32.data(), sizeof(float2) * wt.k32.size(), 0},
+      {wt.k64.data(), sizeof(double2) * wt.k64.size(), 0},
   };
   size_t off = 0;
   for (auto &p : parts) {
@@ -351,10 +410,15 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.ctfT = (const float *)at(13);
   m.xf = (const float *)at(14);
   m.own = (const short *)at(15);
-  m.tgt_off = (const int *)at(16);
-  m.tgt_ent = (const unsigned *)at(17);
-  m.loss_off = (const int *)at(18);
-  m.loss_ent = (const unsigned *)at(19);
+  m.wrows_g = wt.rows_g;
+  m.wrows_l = wt.rows_l;
+  m.we_idx = (const uint2 *)at(16);
+  m.we_x32 = (const float2 *)at(17);
+  m.we_x64 = (const double2 *)at(18);
+  m.we_c32 = (const float2 *)at(19);
+  m.we_c64 = (const double *)at(20);
+  m.we_k32 = (const float2 *)at(21);
+  m.we_k64 = (const double2 *)at(22);
   return FSBM_OK;
 }
 
@@ -366,9 +430,9 @@ void drop_graph(fsbm_coal_t h) {
   h->gkey = GraphKey();
 }
 
-// Workspace for up to npoints points: slots, state, weights, compaction
-// scratch, totals, counters, pending-step counters and the exact path's
-// scratch, in one allocation.
+// Workspace for up to npoints points: slots, state (two buffers for the
+// lane kernels), weights, compaction scratch, totals, counters, pending-step
+// counters and sort keys, in one allocation.
 int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   if (npoints <= h->wpoints) return FSBM_OK;
   const int SB = h->S * h->B;
@@ -396,7 +460,6 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   const size_t o_cnt = take(sizeof(unsigned long long) * 4);
   const size_t o_pend = take(sizeof(int) * cap);
   const size_t o_keys = h->lane ? take(sizeof(unsigned) * cap) : 0;
-  const size_t o_scr = take(sizeof(double) * (size_t)kSlowThreads * 7 * SB);
   drop_graph(h);
   if (h->wmem) hipFree(h->wmem);
   h->wmem = nullptr;
@@ -421,7 +484,6 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   h->ws.counters = (unsigned long long *)(b + o_cnt);
   h->ws.pending = (int *)(b + o_pend);
   h->ws.keys = h->lane ? (unsigned *)(b + o_keys) : nullptr;
-  h->scratch = (double *)(b + o_scr);
   // pending[] is kept at zero by the kernels after this first clear
   e = hipMemset(h->ws.pending, 0, sizeof(int) * cap);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemset");
@@ -527,7 +589,6 @@ int enqueue_call(const Call &c, hipStream_t st) {
     la.dt = c.dt;
   } else {
     wa.ngrids = (int)c.hs.size();
-    int sbmax = 0;
     for (size_t g = 0; g < c.hs.size(); ++g) {
       fsbm_coal_t h = c.hs[g];
       WaveGrid &G = wa.g[g];
@@ -538,13 +599,9 @@ int enqueue_call(const Call &c, hipStream_t st) {
       G.meta = h->ws.meta;
       G.pending = h->ws.pending;
       G.slot_cap = h->ws.slot_cap;
-      sbmax = std::max(sbmax, h->S * h->B);
     }
-    // the first handle is the widest grid of the call (see step_multi), so
-    // its exact-path scratch fits every grid
+    // counters of a multi-grid call are kept in the first handle
     wa.counters = h0->ws.counters;
-    wa.scratch = h0->scratch;
-    wa.scratch_sb = sbmax;
     wa.dt = c.dt;
   }
   // lane kernels: a launch of n steps leaves the state in the buffer it
@@ -572,16 +629,16 @@ int enqueue_call(const Call &c, hipStream_t st) {
     }
     if (prof) HIP_TRY(h0, hipEventRecord(e1, st));
   }
-  // points the fast kernels handed over finish the call on the exact path
-  // (their state is valid in both lane buffers)
-  if (c.nsteps > 0) {
-    if (!c.wave) {
-      la.state = lane_cur;
-      la.state_alt = lane_alt;
-      HIP_TRY(h0, launch_slow_steps(la, h0->ws.slot_cap, st));
-    } else {
-      HIP_TRY(h0, launch_wave_slow(wa, st));
-    }
+  // points the fast kernels handed over finish the call on the exact path:
+  // lane kernels, one lane per point (their state is valid in both lane
+  // buffers); FP32C wave kernel, the FP64 wave kernel on those points
+  if (c.nsteps > 0 && !c.wave) {
+    la.state = lane_cur;
+    la.state_alt = lane_alt;
+    HIP_TRY(h0, launch_slow_steps(la, h0->ws.slot_cap, st));
+  } else if (c.nsteps > 0 && h0->precision == FSBM_FP32C) {
+    wa.pending_only = 1;
+    HIP_TRY(h0, launch_wave_step(wa, h0->precision, c.blocks, st));
   }
   for (size_t g = 0; g < c.hs.size(); ++g) {
     fsbm_coal_t h = c.hs[g];
@@ -794,7 +851,7 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
   }
   if (c.hs.empty() || nsteps == 0) return FSBM_OK;
   HIP_TRY(c.hs[0], hipSetDevice(c.hs[0]->device));
-  // the widest grid goes first: its exact-path scratch serves every grid
+  // the widest grid goes first and keeps the call's counters
   size_t widest = 0;
   for (size_t g = 1; g < c.hs.size(); ++g)
     if (c.hs[g]->S * c.hs[g]->B > c.hs[widest]->S * c.hs[widest]->B)

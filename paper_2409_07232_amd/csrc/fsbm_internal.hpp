@@ -20,7 +20,6 @@ constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
 constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
 constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
-constexpr int kSlowThreads = 4096; // exact-path threads (global scratch)
 // Empty-neighbour guard of the flux fraction: x1 >= ln(1e-60).
 constexpr double kX1Floor = -138.15510557964274;
 
@@ -48,26 +47,31 @@ struct DevModel {
   const double *ctT;
   const float *ctfT;  // [j][i][2]: FP32 Courant number c and c * kLn2f
   // one-point-per-wave kernel: bins owned by each lane ([64][kMaxOwn], -1
-  // padded), and per bin the packed pairs that target it and the packed
-  // partners it loses mass to (CSR)
+  // padded) and, per lane, a stream of gain entries (the pairs landing in
+  // its bins) and a stream of loss entries (the pairs its bins lose mass
+  // to), each entry holding the pair's static data.  Streams are
+  // interleaved by lane (entry r of lane l at r * 64 + l) and padded to the
+  // longest lane: rows [0, wrows_g) are gains, [wrows_g, wrows_g + wrows_l)
+  // losses.  A bin's entries are contiguous in its owner's stream.
   const short *own;
-  const int *tgt_off;
-  const unsigned *tgt_ent;
-  const int *loss_off;
-  const unsigned *loss_ent;
+  int wrows_g, wrows_l;
+  const uint2 *we_idx;    // .x = qa | qb << 16, .y = q_target | flags << 16
+  const float2 *we_x32;   // (x_i, x_j) FP32
+  const double2 *we_x64;  // (x_i, x_j)
+  const float2 *we_c32;   // (c, c ln 2) FP32
+  const double *we_c64;   // c
+  const float2 *we_k32;   // [nbr][rows * 64] (K_{l+1}, K_l - K_{l+1}) FP32
+  const double2 *we_k64;  // same, FP64
 };
 
-// Packed bin pair (a,i) x (b,j) in canonical order (a <= b, i <= j if a == b):
-// i and j (9 bits each), a and b (3 bits each), and flags.
-constexpr unsigned kEntTA = 1u << 24;    // (a,i) is the pair's target bin
-constexpr unsigned kEntTB = 1u << 25;    // (b,j) is the pair's target bin
-constexpr unsigned kEntSideB = 1u << 26; // loss entry: the owner is (b,j)
-constexpr unsigned kEntSelf = 1u << 27;  // loss entry: (a,i) == (b,j)
-__host__ __device__ __forceinline__ unsigned pack_pair(int a, int i, int b,
-                                                       int j) {
-  return (unsigned)i | ((unsigned)j << 9) | ((unsigned)a << 18) |
-         ((unsigned)b << 21);
-}
+// Flags of a wave-stream entry for the pair (a,i) x (b,j), qa = a B + i,
+// qb = b B + j, merged mass landing in q_target.
+constexpr unsigned kWValid = 1u;  // a pair (not padding)
+constexpr unsigned kWTA = 2u;     // qa is the target bin
+constexpr unsigned kWTB = 4u;     // qb is the target bin
+constexpr unsigned kWSelf = 8u;   // qa == qb (same species and bin)
+constexpr unsigned kWSideB = 16u; // loss entry: the owner is qb (else qa)
+constexpr unsigned kWFlux = 32u;  // the target is not the top bin: flux
 
 // Compaction results, written on the device (graph-capturable: no host
 // round trip).  Slots of one pressure bracket are contiguous and padded to a
@@ -125,11 +129,10 @@ struct WaveArgs {
   WaveGrid g[kMaxGrids];
   int ngrids;
   unsigned long long *counters;
-  double *scratch;  // exact path: [kSlowThreads][7 * max S*B]
-  int scratch_sb;   // max S*B the scratch was sized for
   double dt;
   int nsteps;       // steps in this launch
   int steps_left;   // steps of the call left when this launch starts
+  int pending_only; // FP64 steps for the points marked pending only
 };
 
 // Arguments of the step kernels.
@@ -189,10 +192,10 @@ hipError_t launch_lane_step(const StepArgs &a, int precision,
                             int waves_per_block, int max_slots,
                             hipStream_t st);
 // One-point-per-wave kernels (any species set and grid), over one or more
-// grids, and their exact FP64 path.
+// grids; they run the positivity limiter's second pass themselves (FP32C:
+// in the FP64 follow-up launch with pending_only set).
 hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
                             hipStream_t st);
-hipError_t launch_wave_slow(const WaveArgs &a, hipStream_t st);
 
 // Exact FP64 steps (with the positivity limiter) for every slot whose fast
 // kernel stopped on an over-demand bound: once a point leaves the fast path

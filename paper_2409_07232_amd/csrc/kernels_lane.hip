@@ -310,18 +310,17 @@ __global__ void __launch_bounds__(kWave *WPB)
     const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
     bool flag = false;
     unsigned step_pairs = 0;
-    // S6 for bin k: FP64 update from the compensated gain (gs, gc) and the
-    // compensated losses, written to the other buffer
-    auto finish = [&](int k, float gs, float gc, double Nk) {
-      const double g = (double)gs + (double)gc;
+    // S6 for bin k: FP64 update from the FP64 gain g and the compensated
+    // losses, written to the other buffer
+    auto finish = [&](int k, double g, double Nk) {
       const double l = (double)Ls.get(k) + (double)Lc.get(k);
       const double Mk = ldexp(__dmul_rn(Nk, x1), k);
       double Mn = Mk + (g - l) * Mtot;
       Mn = Mn < 0.0 ? 0.0 : Mn;
       if (live) so[k * kWave + lane] = ldexp(Mn / x1, -k);
     };
-    // gain of bin j+1 from its own row, carried down one row
-    float gs = 0.0f, gc = 0.0f;
+    // gain of bin j+1 from its own row (FP64), carried down one row
+    double g = 0.0;
     // state of bin j+1, loaded one row ahead of its update (rows run over
     // the union [lo, hi] of the wave's active bins; bins lo..hi+1 change)
     double Nnext = (hi + 1 <= B - 1) ? sb[(hi + 1) * kWave + lane] : 0.0;
@@ -329,14 +328,17 @@ __global__ void __launch_bounds__(kWave *WPB)
     for (int j = hi; j >= lo; --j) {
       const double Nj1 = Nnext;
       Nnext = sb[j * kWave + lane];
-      float fs = 0.0f, fc = 0.0f;  // flux leaving bin j for j+1
-      float self2 = 0.0f;          // self-pair mass, bin j -> j+1
-      float ns = 0.0f, nc = 0.0f;  // gain of bin j from row j
+      double gj = 0.0;  // gain of bin j from row j
       if (bit_of(uni_lo, uni_hi, j)) {
+        float fs = 0.0f, fc = 0.0f;  // flux leaving bin j for j+1
+        float self2 = 0.0f;          // self-pair mass, bin j -> j+1
         const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
         const uint32_t cl = uni_lo & (uint32_t)below_mask;
         const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
         const float mj = m.get(j);
+        // guarded log argument below: 2^-126 keeps it positive in lanes
+        // where bin j is empty (their pair amounts are zero)
+        const float mjg = mj + 0x1p-126f;
         const float tj = (tau * mj) * ldc(ixf + j);  // A = K m_i tj
         // the pressure weight folded into the row factor:
         // tj K = tj K_{l+1} + (tj w) (K_l - K_{l+1})
@@ -347,29 +349,43 @@ __global__ void __launch_bounds__(kWave *WPB)
         const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
         const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, c ln 2)
         float as = 0.0f, ac = 0.0f;  // mass arriving in bin j
+        // columns in chunks of 8: the chunk's table entries (kernel pair and
+        // Courant pair per column) are fetched with a few wide scalar loads
+        // before its pairs, instead of one load and wait per pair
 #pragma unroll
-        for (int i = 0; i < B - 1; ++i) {
-          if (!bit_of(cl, ch, i)) continue;
-          const float *e = Kj + i * 2;
-          const float tK = __builtin_fmaf(ldc(e + 1), tjw, tj * ldc(e));
-          const float A = tK * m.get(i);
-          // x_j / x_i = 2^(j-i) exactly on the doubling grid
-          const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
-          const float Sm = A + Bm;
-          {
-            float s = Ls.get(i), c = Lc.get(i);
-            comp_add_pos(s, c, A);
-            Ls.set(i, s);
-            Lc.set(i, c);
+        for (int i0 = 0; i0 < B - 1; i0 += 8) {
+          const uint32_t chunk = (i0 < 32) ? ((cl >> i0) & 0xffu)
+                                           : ((ch >> (i0 - 32)) & 0xffu);
+          if (!chunk) continue;
+          float kk[16], cc[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const bool in = i0 * 2 + u < 2 * (B - 1);  // inside row j
+            kk[u] = in ? ldc(Kj + i0 * 2 + u) : 0.0f;
+            cc[u] = in ? ldc(cj + i0 * 2 + u) : 0.0f;
           }
-          comp_add_pos(as, ac, A);
-          if (has_flux) {
-            const float den = __builtin_fmaxf(mj + Sm, 0x1p-120f);
-            float lam = lmj1 - __builtin_amdgcn_logf(den);
-            lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
-            const float c = ldc(cj + 2 * i), cl2 = ldc(cj + 2 * i + 1);
-            const float F = flux_fraction_f32(c, cl2, lam) * Sm;
-            comp_add_pos(fs, fc, F);
+#pragma unroll
+          for (int i = i0; i < i0 + 8 && i < B - 1; ++i) {
+            if (!bit_of(cl, ch, i)) continue;
+            const int u = 2 * (i - i0);
+            const float tK = __builtin_fmaf(kk[u + 1], tjw, tj * kk[u]);
+            const float A = tK * m.get(i);
+            // x_j / x_i = 2^(j-i) exactly on the doubling grid
+            const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
+            const float Sm = A + Bm;
+            {
+              float s = Ls.get(i), c = Lc.get(i);
+              comp_add_pos(s, c, A);
+              Ls.set(i, s);
+              Lc.set(i, c);
+            }
+            comp_add_pos(as, ac, A);
+            if (has_flux) {
+              float lam = lmj1 - __builtin_amdgcn_logf(mjg + Sm);
+              lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
+              const float F = flux_fraction_f32(cc[u], cc[u + 1], lam) * Sm;
+              comp_add_pos(fs, fc, F);
+            }
           }
         }
         // self pair: transfer 2A from bin j to bin j+1 (exact hit, no flux)
@@ -383,23 +399,17 @@ __global__ void __launch_bounds__(kWave *WPB)
         // leaving bin j (>= the negative merged nets); FP32 margin.
         const float demand = (Ls.get(j) + Lc.get(j)) + self2 + (fs + fc);
         flag = flag || (mj > 0.0f && demand > mj * (1.0f - 1e-5f));
-        comp_add(ns, nc, as);
-        comp_add(ns, nc, ac);
-        comp_add(ns, nc, -fs);
-        comp_add(ns, nc, -fc);
-        comp_add(ns, nc, -self2);
+        // the row's compensated sums meet in FP64: bin j keeps the mass
+        // arriving from smaller partners less what it passes on to j+1
+        const double out = ((double)fs + (double)fc) + (double)self2;
+        gj = ((double)as + (double)ac) - out;
+        if (j + 1 <= B - 1) g += out;
         step_pairs += row_pairs<B>(act, j);
-        if (j + 1 <= B - 1) {
-          comp_add(gs, gc, fs);
-          comp_add(gs, gc, fc);
-          comp_add(gs, gc, self2);
-        }
       }
-      if (j + 1 <= B - 1) finish(j + 1, gs, gc, Nj1);
-      gs = ns;
-      gc = nc;
+      if (j + 1 <= B - 1) finish(j + 1, g, Nj1);
+      g = gj;
     }
-    if (uni) finish(lo, gs, gc, Nnext);
+    if (uni) finish(lo, g, Nnext);
     // bins outside [lo, hi+1] take no part in this step: carried over
     if (live) {
 #pragma unroll 1

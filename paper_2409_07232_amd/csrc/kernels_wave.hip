@@ -1,8 +1,7 @@
 // kernels_wave.hip -- one grid point per wave: the collision step for any
 // species set and any bin grid (several particle types with their pair
-// kernels and product rules, refined grids up to hundreds of bins; Sec. III:
-// "33 bins ... extendable to a few hundreds"), over one or several grids in
-// one persistent launch.
+// kernels and product rules; the 33 bins per type of Sec. III refined to a
+// few hundred), over one or several grids in one persistent launch.
 //
 // Mapping (gfx950):
 //  * a wave (one 64-thread block) owns one point at a time and loops over
@@ -11,26 +10,35 @@
 //    built at create time; each lane owns up to kMaxOwn bins and keeps their
 //    accumulators in registers;
 //  * the point's masses, numbers and log-masses sit in LDS for all lanes;
-//  * gains: the owner of bin (P,k) walks the precomputed list of pairs whose
-//    merged mass lands in (P,k) and evaluates each such pair once (collided
-//    masses, exponential-profile flux fraction); the flux leaving (P,k) for
-//    (P,k+1) is handed over through LDS;
+//  * each lane walks two precomputed streams of pair entries, interleaved by
+//    lane so that entry r of all 64 lanes is one coalesced load and the
+//    addresses never depend on loaded data; an entry carries the pair's
+//    bins, flags, bin masses, Courant numbers and interpolation pairs;
+//  * gains: the owner of bin (P,k) evaluates each pair whose merged mass
+//    lands in (P,k) once (collided masses, exponential-profile flux
+//    fraction); the flux leaving (P,k) for (P,k+1) is handed over through
+//    LDS;
 //  * losses: the owner of a source bin recomputes the same collided mass of
 //    each of its pairs (the identical operation sequence, hence the identical
 //    value), so every transfer is applied symmetrically and no cross-lane
 //    accumulation or atomic is needed; results do not depend on timing;
-//  * a conservative over-demand bound per bin (losses + outgoing flux)
-//    hands the rare point that may need the positivity limiter to the exact
-//    FP64 path (wave_slow, global scratch).
+//  * a bin's entries are contiguous in its owner's stream: a running sum in
+//    registers is stored to LDS once per bin;
+//  * positivity limiter: the first pass also sums each bin's demand (its
+//    negative merged nets); if any bin is over-demanded the wave runs the
+//    second pass of the method itself, every pair scaled by the smallest
+//    sigma = M / D over the bins where the pair's net is negative.
 // FP64 mode: the method in FP64 with FP64 sums.  FP32C mode: normalised
 // masses, FP32 pair arithmetic, compensated FP32 sums (TwoSum error
-// capture), FP64 totals and FP64 update.
+// capture), FP64 totals and FP64 update; a point at which the limiter fires
+// takes that and every remaining step of the call in FP64 mode (a follow-up
+// launch over those points only), since emptying a bin by cancellation
+// needs FP64 to stay conservative and positive.
 #include <float.h>
 
 #include <type_traits>
 
 #include "device_common.hpp"
-#include "slow_path.hpp"
 
 #pragma clang fp contract(off)
 
@@ -62,90 +70,138 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
-__device__ __forceinline__ int species_pair(int S, int a, int b) {
-  return a * S - (a * (a - 1)) / 2 + (b - a);
-}
-
-struct PairIdx {
-  int i, j, a, b;
-};
-
-__device__ __forceinline__ PairIdx unpack(unsigned e) {
-  PairIdx p;
-  p.i = (int)(e & 511u);
-  p.j = (int)((e >> 9) & 511u);
-  p.a = (int)((e >> 18) & 7u);
-  p.b = (int)((e >> 21) & 7u);
-  return p;
-}
-
-// Collided amounts of one pair in FP64: A leaves (a,i), Bm leaves (b,j).
-__device__ __forceinline__ void amounts_f64(const DevModel &m, int br,
-                                            double w, double dt,
-                                            const double *Nv,
-                                            const PairIdx &p, double &A,
-                                            double &Bm) {
-  const int B = m.B;
-  const int ab = species_pair(m.S, p.a, p.b);
-  const double *e =
-      m.Kd + ((((size_t)ab * m.nbr + br) * B + p.i) * B + p.j) * 2;
-  const double K = fma(e[1], w, e[0]);
-  double C = dt * K * Nv[p.a * B + p.i] * Nv[p.b * B + p.j];
-  if (p.a == p.b && p.i == p.j) C *= 0.5;
-  A = C * m.x[p.i];
-  Bm = C * m.x[p.j];
+// Collided amounts of one stream entry: A leaves qa, Bm leaves qb.
+__device__ __forceinline__ void entry_amounts(double K, double dt,
+                                              const double *Nv, int qa,
+                                              int qb, bool self, double2 x,
+                                              double &A, double &Bm) {
+  double C = dt * K * Nv[qa] * Nv[qb];
+  if (self) C *= 0.5;
+  A = C * x.x;
+  Bm = C * x.y;
 }
 
 // The same in FP32 on numbers normalised by the point's mass (tau = dt
 // M_tot): amounts come out normalised by M_tot.
-__device__ __forceinline__ void amounts_f32(const DevModel &m, int br,
-                                            float wf, float tau,
-                                            const float *nv,
-                                            const PairIdx &p, float &A,
-                                            float &Bm) {
-  const int B = m.B;
-  const int ab = species_pair(m.S, p.a, p.b);
-  const float *e =
-      m.Kf + ((((size_t)ab * m.nbr + br) * B + p.i) * B + p.j) * 2;
-  const float K = __builtin_fmaf(e[1], wf, e[0]);
-  float C = ((tau * K) * nv[p.a * B + p.i]) * nv[p.b * B + p.j];
-  if (p.a == p.b && p.i == p.j) C *= 0.5f;
-  A = C * m.xf[p.i];
-  Bm = C * m.xf[p.j];
+__device__ __forceinline__ void entry_amounts(float K, float tau,
+                                              const float *n, int qa, int qb,
+                                              bool self, float2 x, float &A,
+                                              float &Bm) {
+  float C = ((tau * K) * n[qa]) * n[qb];
+  if (self) C *= 0.5f;
+  A = C * x.x;
+  Bm = C * x.y;
 }
 
-// One step of one point by one wave.  Returns false (state untouched) if
-// the over-demand bound fired and the exact path must take the step.
+// Flux that a pair with merged mass Sm landing in bin qt moves on to qt+1;
+// the gain and the loss side call the same function with the same inputs.
+__device__ __forceinline__ double entry_flux(bool has_flux, const double *Mt,
+                                             const double *lnM, int qt,
+                                             double c, double Sm) {
+  if (!has_flux) return 0.0;
+  const double den = fmax(Mt[qt] + Sm, DBL_MIN);
+  const double x1 = fmax(lnM[qt + 1] - log(den), kX1Floor);
+  return flux_fraction_f64(c, x1) * Sm;
+}
+
+__device__ __forceinline__ float entry_flux(bool has_flux, const float *m,
+                                            const float *lm, int qt,
+                                            float2 c, float Sm) {
+  if (!has_flux) return 0.0f;
+  const float den = __builtin_fmaxf(m[qt] + Sm, 0x1p-120f);
+  float lam = lm[qt + 1] - __builtin_amdgcn_logf(den);
+  lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
+  return flux_fraction_f32(c.x, c.y, lam) * Sm;
+}
+
+// Limiter scale of a pair: the smallest sigma over the bins where the pair's
+// net is negative.  A source bin that does not receive the merged mass has
+// net -A (or -Bm); a source bin that does has net Bm - F (or A - F).
+template <typename T>
+__device__ __forceinline__ T pair_scale(const T *sg, int qa, int qb, bool ta,
+                                        bool tb, T A, T Bm, T F) {
+  T s = (T)1;
+  const bool na = ta ? (Bm - F < (T)0) : (A > (T)0);
+  const bool nb = tb ? (A - F < (T)0) : (Bm > (T)0);
+  if (na) s = sg[qa] < s ? sg[qa] : s;
+  if (nb) s = sg[qb] < s ? sg[qb] : s;
+  return s;
+}
+
+// Per-bin accumulators of a pass in LDS: FP64 one array each, FP32 a
+// (sum, compensation) pair of arrays each.
 template <bool F32>
-__device__ bool point_step(const DevModel &m, double *st, double w, int br,
-                           double dt, unsigned char *lds,
-                           unsigned long long &npairs) {
+struct PassLds;
+template <>
+struct PassLds<false> {
+  double *gain, *fout, *loss, *dneg;
+  __device__ void store(double *arr, int q, const AccF64 &a) const {
+    arr[q] = a.v;
+  }
+  __device__ double read(const double *arr, int q) const { return arr[q]; }
+};
+template <>
+struct PassLds<true> {
+  float *gain, *fout, *loss, *dneg;  // each [2][SB]: sums then compensations
+  int SB;
+  __device__ void store(float *arr, int q, const AccF32 &a) const {
+    arr[q] = a.s;
+    arr[SB + q] = a.c;
+  }
+  __device__ double read(const float *arr, int q) const {
+    return (double)arr[q] + (double)arr[SB + q];
+  }
+};
+
+// One step of one point by one wave (S1-S6).  Returns 1 if the limiter ran;
+// in FP32C mode it returns 2 and leaves the point untouched when the
+// limiter is needed (the caller takes that step in FP64 mode).
+template <bool F32>
+__device__ unsigned point_step(const DevModel &m, const short *own_in,
+                               double *st, double w, int br, double dt,
+                               unsigned char *lds,
+                               unsigned long long &npairs) {
+  // owned bins, opaque per step: keeps the compiler from holding per-bin
+  // addresses in registers across steps
+  int own[kMaxOwn];
+#pragma unroll
+  for (int o = 0; o < kMaxOwn; ++o) {
+    own[o] = own_in[o];
+    asm volatile("" : "+v"(own[o]));
+  }
   typedef typename std::conditional<F32, AccF32, AccF64>::type Acc;
+  typedef typename std::conditional<F32, float, double>::type Real;
+  typedef typename std::conditional<F32, float2, double2>::type Real2;
   const int lane = threadIdx.x;
   const int B = m.B, SB = m.S * m.B;
-  // LDS: FP64 mode Mt, Nv, lnM, fout (doubles); FP32 mode m, n, lm, fs, fc
-  double *Mt_l = (double *)lds;
-  double *Nv_l = Mt_l + SB;
-  double *ln_l = Nv_l + SB;
-  double *fo_l = ln_l + SB;
-  float *m_l = (float *)lds;
-  float *n_l = m_l + SB;
-  float *lm_l = n_l + SB;
-  float *fs_l = lm_l + SB;
-  float *fc_l = fs_l + SB;
-  const short *own = m.own + lane * kMaxOwn;
+  // LDS (8 SB doubles): masses, numbers, log-masses, then the pass sums and
+  // the limiter factors
+  Real *mass = (Real *)lds;
+  Real *nv = mass + SB;
+  Real *lnm = nv + SB;
+  Real *acc0 = lnm + SB;
+  PassLds<F32> P;
+  if constexpr (F32) {
+    P.SB = SB;
+    P.gain = acc0;
+    P.fout = acc0 + 2 * SB;
+    P.loss = acc0 + 4 * SB;
+    P.dneg = acc0 + 6 * SB;
+  } else {
+    P.gain = acc0;
+    P.fout = acc0 + SB;
+    P.loss = acc0 + 2 * SB;
+    P.dneg = acc0 + 3 * SB;
+  }
+  double *sg = (double *)(lds + (size_t)7 * SB * sizeof(double));
 
-  // S1/S2: owned bins, FP64 total, activity
-  double Mown[kMaxOwn];
+  // S1/S2: owned bins, FP64 total, activity (a bin's mass is recomputed
+  // from its state where needed rather than kept in registers)
   double part = 0.0;
 #pragma unroll
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
-    Mown[o] = 0.0;
-    if (q >= 0) {
-      Mown[o] = st[q] * m.x[q % B];
-      part += Mown[o];
-    }
+    if (q >= 0) part += st[q] * m.x[q % B];
   }
   const double Mtot = wave_sum_f64(part);
   const double thr = m.theta * Mtot;
@@ -154,239 +210,277 @@ __device__ bool point_step(const DevModel &m, double *st, double w, int br,
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
-    const double Mq = Mown[o];
+    const double Mq = st[q] * m.x[q % B];
     const bool act = Mq > 0.0 && Mq >= thr;
     const double Mt = act ? Mq : 0.0;
     if constexpr (F32) {
       const float mq = (float)(Mt * inv);
-      m_l[q] = mq;
-      n_l[q] = (float)((act ? st[q] : 0.0) * inv);
-      lm_l[q] = __builtin_amdgcn_logf(mq);
+      mass[q] = mq;
+      nv[q] = (float)((act ? st[q] : 0.0) * inv);
+      lnm[q] = __builtin_amdgcn_logf(mq);
     } else {
-      Mt_l[q] = Mt;
-      Nv_l[q] = act ? st[q] : 0.0;
-      ln_l[q] = log(Mt);
+      mass[q] = Mt;
+      nv[q] = act ? st[q] : 0.0;
+      lnm[q] = log(Mt);
     }
-  }
-  __syncthreads();
-  const float wf = (float)w;
-  const float tau = (float)(dt * Mtot);
-
-  // S3/S4 gains: pairs landing in each owned bin, flux to the next bin
-  Acc gain[kMaxOwn], fout[kMaxOwn], loss[kMaxOwn];
-#pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    gain[o].zero();
-    fout[o].zero();
-    loss[o].zero();
-  }
-#pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int q = own[o];
-    if (q < 0) continue;
-    const int k = q % B;
-    const bool has_flux = k <= B - 2;
-    const int e0 = m.tgt_off[q], e1 = m.tgt_off[q + 1];
-    for (int e = e0; e < e1; ++e) {
-      const unsigned ent = m.tgt_ent[e];
-      const PairIdx p = unpack(ent);
-      const int qa = p.a * B + p.i, qb = p.b * B + p.j;
-      if constexpr (F32) {
-        if (m_l[qa] == 0.0f || m_l[qb] == 0.0f) continue;
-        float A, Bm;
-        amounts_f32(m, br, wf, tau, n_l, p, A, Bm);
-        float F = 0.0f;
-        if (has_flux) {
-          const float Sm = A + Bm;
-          const float den = __builtin_fmaxf(m_l[q] + Sm, 0x1p-120f);
-          float lam = lm_l[q + 1] - __builtin_amdgcn_logf(den);
-          lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
-          const float c = m.ctf[p.i * B + p.j];
-          F = flux_fraction_f32(c, c * kLn2f, lam) * Sm;
-        }
-        if (!(ent & kEntTA)) gain[o].add(A);
-        if (!(ent & kEntTB)) gain[o].add(Bm);
-        gain[o].add(-F);
-        fout[o].add(F);
-      } else {
-        if (Mt_l[qa] == 0.0 || Mt_l[qb] == 0.0) continue;
-        double A, Bm;
-        amounts_f64(m, br, w, dt, Nv_l, p, A, Bm);
-        double F = 0.0;
-        if (has_flux) {
-          const double Sm = A + Bm;
-          const double den = fmax(Mt_l[q] + Sm, DBL_MIN);
-          const double x1 = fmax(ln_l[q + 1] - log(den), kX1Floor);
-          F = flux_fraction_f64(m.ct[p.i * B + p.j], x1) * Sm;
-        }
-        // the pair's combined contribution to its target in one rounding
-        // (a target that is also a source keeps the other source's mass)
-        const double keep =
-            (ent & kEntTA) ? Bm : ((ent & kEntTB) ? A : A + Bm);
-        gain[o].add(keep - F);
-        fout[o].add(F);
-      }
-      ++npairs;
-    }
-  }
-  // hand the flux of bin (P,k) to the owner of (P,k+1)
-  __syncthreads();
-#pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int q = own[o];
-    if (q < 0) continue;
+    // the pass sums of a bin with no entries stay zero (its owner writes
+    // every other bin's sums in the passes)
     if constexpr (F32) {
-      fs_l[q] = fout[o].s;
-      fc_l[q] = fout[o].c;
+      P.gain[q] = P.gain[SB + q] = 0.0f;
+      P.fout[q] = P.fout[SB + q] = 0.0f;
+      P.loss[q] = P.loss[SB + q] = 0.0f;
+      P.dneg[q] = P.dneg[SB + q] = 0.0f;
     } else {
-      fo_l[q] = fout[o].v;
+      P.gain[q] = P.fout[q] = P.loss[q] = P.dneg[q] = 0.0;
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int q = own[o];
-    if (q < 0 || q % B == 0) continue;
-    if constexpr (F32) {
-      gain[o].add(fs_l[q - 1]);
-      gain[o].add(fc_l[q - 1]);
-    } else {
-      gain[o].add(fo_l[q - 1]);
-    }
+  Real wr, tdt;
+  if constexpr (F32) {
+    wr = (float)w;
+    tdt = (float)(dt * Mtot);
+  } else {
+    wr = w;
+    tdt = dt;
+  }
+  const size_t nrows = (size_t)(m.wrows_g + m.wrows_l) * kWave;
+  const Real2 *xe;
+  const Real2 *ke;
+  if constexpr (F32) {
+    xe = m.we_x32;
+    ke = m.we_k32 + (size_t)br * nrows;
+  } else {
+    xe = m.we_x64;
+    ke = m.we_k64 + (size_t)br * nrows;
   }
 
-  // losses: the same collided amounts, seen from the source bins
-#pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int q = own[o];
-    if (q < 0) continue;
-    bool active;
-    if constexpr (F32)
-      active = m_l[q] != 0.0f;
-    else
-      active = Mt_l[q] != 0.0;
-    if (!active) continue;
-    const int e0 = m.loss_off[q], e1 = m.loss_off[q + 1];
-    for (int e = e0; e < e1; ++e) {
-      const unsigned ent = m.loss_ent[e];
-      const PairIdx p = unpack(ent);
-      const int partner = (ent & kEntSideB) ? p.a * B + p.i : p.b * B + p.j;
-      if constexpr (F32) {
-        if (m_l[partner] == 0.0f) continue;
-        float A, Bm;
-        amounts_f32(m, br, wf, tau, n_l, p, A, Bm);
-        if (ent & kEntSelf) {
-          loss[o].add(A);
-          loss[o].add(Bm);
-        } else {
-          loss[o].add((ent & kEntSideB) ? Bm : A);
+  bool lim = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    // S3/S4 gains over this lane's gain stream
+    {
+      Acc g, f, d;
+      g.zero();
+      f.zero();
+      d.zero();
+      int cur = -1;
+#pragma unroll 2
+      for (int r = 0; r < m.wrows_g; ++r) {
+        const size_t pos = (size_t)r * kWave + lane;
+        const uint2 id = m.we_idx[pos];
+        const unsigned fl = id.y >> 16;
+        if (!(fl & kWValid)) continue;  // padding at the stream's end
+        const int qt = (int)(id.y & 0xffffu);
+        if (qt != cur) {
+          if (cur >= 0) {
+            P.store(P.gain, cur, g);
+            P.store(P.fout, cur, f);
+            if (pass == 0) P.store(P.dneg, cur, d);
+          }
+          cur = qt;
+          g.zero();
+          f.zero();
+          d.zero();
         }
-      } else {
-        if (Mt_l[partner] == 0.0) continue;
-        double A, Bm;
-        amounts_f64(m, br, w, dt, Nv_l, p, A, Bm);
-        if (ent & kEntSelf) {
-          loss[o].add(A);
-          loss[o].add(Bm);
+        const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
+        if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
+        const Real2 kk = ke[pos];
+        Real A, Bm;
+        entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb,
+                      (fl & kWSelf) != 0, xe[pos], A, Bm);
+        Real F;
+        if constexpr (F32)
+          F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c32[pos],
+                         A + Bm);
+        else
+          F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c64[pos],
+                         A + Bm);
+        const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+        if (pass == 1) {
+          const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A, Bm,
+                                     F);
+          A *= sc;
+          Bm *= sc;
+          F *= sc;
+        }
+        if constexpr (F32) {
+          // exact transfers: the same rounded amounts as the source side
+          if (!ta) g.add(A);
+          if (!tb) g.add(Bm);
+          g.add(-F);
         } else {
-          loss[o].add((ent & kEntSideB) ? Bm : A);
+          // the pair's combined contribution to its target in one rounding
+          // (a target that is also a source keeps the other source's mass)
+          const double keep = ta ? Bm : (tb ? A : A + Bm);
+          g.add(keep - F);
+        }
+        f.add(F);
+        if (pass == 0) {
+          if (ta || tb) {
+            const Real keep = ta ? Bm : A;
+            if (F > keep) d.add(F - keep);
+          }
+          ++npairs;
         }
       }
+      if (cur >= 0) {
+        P.store(P.gain, cur, g);
+        P.store(P.fout, cur, f);
+        if (pass == 0) P.store(P.dneg, cur, d);
+      }
     }
-  }
-
-  // S5 bound: demand <= losses + outgoing flux (the merged net of a bin
-  // that is also its pair's target is A - F >= -F)
-  bool flag = false;
+    // losses over this lane's loss stream: the same collided amounts, seen
+    // from the source bins
+    {
+      Acc lo;
+      lo.zero();
+      int cur = -1;
+#pragma unroll 2
+      for (int r = m.wrows_g; r < m.wrows_g + m.wrows_l; ++r) {
+        const size_t pos = (size_t)r * kWave + lane;
+        const uint2 id = m.we_idx[pos];
+        const unsigned fl = id.y >> 16;
+        if (!(fl & kWValid)) continue;
+        const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
+        const bool sideb = (fl & kWSideB) != 0;
+        const int q = sideb ? qb : qa;
+        if (q != cur) {
+          if (cur >= 0) P.store(P.loss, cur, lo);
+          cur = q;
+          lo.zero();
+        }
+        if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
+        const Real2 kk = ke[pos];
+        const bool self = (fl & kWSelf) != 0;
+        Real A, Bm;
+        entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb, self, xe[pos], A,
+                      Bm);
+        if (pass == 1) {
+          // the pair's scale, as its target's owner computes it
+          const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+          const int qt = (int)(id.y & 0xffffu);
+          Real F = (Real)0;
+          if (ta || tb) {
+            if constexpr (F32)
+              F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
+                             m.we_c32[pos], A + Bm);
+            else
+              F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
+                             m.we_c64[pos], A + Bm);
+          }
+          const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A, Bm,
+                                     F);
+          A *= sc;
+          Bm *= sc;
+        }
+        if (self) {
+          lo.add(A);
+          lo.add(Bm);
+        } else {
+          lo.add(sideb ? Bm : A);
+        }
+      }
+      if (cur >= 0) P.store(P.loss, cur, lo);
+    }
+    // every pass sum and outgoing flux visible to all lanes
+    __syncthreads();
+    if (pass == 1) break;
+    // S5: demand of each owned bin = its negative merged nets; sigma where
+    // the demand exceeds the mass
+    bool over = false;
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int q = own[o];
-    if (q < 0) continue;
-    double Mq;
-    if constexpr (F32)
-      Mq = (double)m_l[q];
-    else
-      Mq = Mt_l[q];
-    if (Mq == 0.0) continue;
-    const double demand = loss[o].val() + fout[o].val();
-    flag = flag || demand > Mq * (F32 ? (1.0 - 1e-5) : (1.0 - 1e-9));
+    for (int o = 0; o < kMaxOwn; ++o) {
+      const int q = own[o];
+      if (q < 0) continue;
+      const double Mq = (double)mass[q];
+      const double D = P.read(P.loss, q) + P.read(P.dneg, q);
+      const bool od = D > Mq;
+      over = over || od;
+      if constexpr (!F32) sg[q] = od ? Mq / D : 1.0;
+    }
+    lim = __any(over);
+    if (!lim) break;
+    __syncthreads();  // sigma visible before the second pass
+    if constexpr (F32) return 2u;
   }
-  const bool any_flag = __any(flag);
-  __syncthreads();  // LDS is rewritten by the next step
-  if (any_flag) return false;
 
   // S6: FP64 update of the owned bins
 #pragma unroll
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
-    double net = gain[o].val() - loss[o].val();
+    double gq;
+    if constexpr (F32) {
+      AccF32 ga;
+      ga.s = P.gain[q];
+      ga.c = P.gain[SB + q];
+      if (q % B != 0) {
+        ga.add(P.fout[q - 1]);
+        ga.add(P.fout[SB + q - 1]);
+      }
+      gq = ga.val();
+    } else {
+      gq = P.gain[q];
+      if (q % B != 0) gq += P.fout[q - 1];
+    }
+    double net = gq - P.read(P.loss, q);
     if constexpr (F32) net *= Mtot;
-    double Mn = Mown[o] + net;
+    const double xq = m.x[q % B];
+    double Mn = st[q] * xq + net;
     Mn = Mn < 0.0 ? 0.0 : Mn;
-    st[q] = Mn / m.x[q % B];
+    st[q] = Mn / xq;
   }
-  return true;
+  __syncthreads();  // LDS is rewritten by the next step
+  return lim ? 1u : 0u;
 }
 
+// Persistent over the compacted slots of every grid.  FP32C: a point whose
+// step needs the limiter is marked pending (steps of the call left) and
+// skipped from then on.  pending_only: FP64 steps for the marked points.
 template <bool F32>
-__global__ void __launch_bounds__(kWave) wave_step(WaveArgs a) {
+__global__ void __launch_bounds__(kWave)
+    __attribute__((amdgpu_waves_per_eu(2))) wave_step(WaveArgs a) {
   extern __shared__ unsigned char lds[];
-  unsigned long long npairs = 0;
+  unsigned long long npairs = 0, nlim = 0, nfp64 = 0;
   for (int g = 0; g < a.ngrids; ++g) {
     const WaveGrid &G = a.g[g];
     const DevModel &m = G.m;
     const int SB = m.S * m.B;
     const int nslots = G.meta->nslots;
+    short own[kMaxOwn];
+#pragma unroll
+    for (int o = 0; o < kMaxOwn; ++o) own[o] = m.own[threadIdx.x * kMaxOwn + o];
     for (int slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
       const int pt = G.slot_point[slot];
-      // padding, or a point handed to the exact path earlier in the call
-      if (pt < 0 || G.pending[slot] != 0) continue;
+      if (pt < 0) continue;  // padding
+      const int pend = G.pending[slot];
+      if (a.pending_only ? pend <= 0 : pend != 0) continue;
       int br = 0;
       for (int b = 1; b < m.nbr; ++b)
         if (slot >= G.meta->bucket_base[b]) br = b;
       const double w = G.wgt[slot];
       double *st = G.state + (size_t)slot * SB;
-      for (int step = 0; step < a.nsteps; ++step) {
-        unsigned long long pc = 0;
-        const bool ok = point_step<F32>(m, st, w, br, a.dt, lds, pc);
-        if (!ok) {
+      const int n = a.pending_only ? pend : a.nsteps;
+      for (int step = 0; step < n; ++step) {
+        const unsigned r =
+            point_step<F32>(m, own, st, w, br, a.dt, lds, npairs);
+        if (F32 && r == 2u) {
           if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
           break;
         }
-        npairs += pc;
+        nlim += r;
+      }
+      if (a.pending_only) {
+        nfp64 += (unsigned long long)pend;
+        if (threadIdx.x == 0) G.pending[slot] = 0;
       }
     }
   }
   npairs = wave_sum_u64(npairs);
-  if (threadIdx.x == 0 && npairs) atomicAdd(&a.counters[0], npairs);
-}
-
-// Exact FP64 steps for points the fast kernel handed over.
-__global__ void __launch_bounds__(64) wave_slow(WaveArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double *work = a.scratch + (size_t)t * 7 * a.scratch_sb;
-  unsigned long long pairs = 0, lim = 0, fb = 0;
-  for (int g = 0; g < a.ngrids; ++g) {
-    const WaveGrid &G = a.g[g];
-    const int SB = G.m.S * G.m.B;
-    const int nslots = G.meta->nslots;
-    for (int slot = t; slot < nslots; slot += kSlowThreads) {
-      const int n = G.pending[slot];
-      if (n <= 0) continue;
-      int br = 0;
-      for (int b = 1; b < G.m.nbr; ++b)
-        if (slot >= G.meta->bucket_base[b]) br = b;
-      for (int k = 0; k < n; ++k)
-        lim += slow_step_core(G.m, G.state + (size_t)slot * SB, 1,
-                              G.wgt[slot], br, a.dt, &pairs, work);
-      fb += (unsigned long long)n;
-      G.pending[slot] = 0;
-    }
+  if (threadIdx.x == 0) {
+    if (npairs) atomicAdd(&a.counters[0], npairs);
+    if (nlim) atomicAdd(&a.counters[1], nlim);
+    if (nfp64) atomicAdd(&a.counters[2], nfp64);
   }
-  if (pairs) atomicAdd(&a.counters[0], pairs);
-  if (lim) atomicAdd(&a.counters[1], lim);
-  if (fb) atomicAdd(&a.counters[2], fb);
 }
 
 }  // namespace
@@ -396,18 +490,16 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
   int sb = 0;
   for (int g = 0; g < a.ngrids; ++g)
     sb = a.g[g].m.S * a.g[g].m.B > sb ? a.g[g].m.S * a.g[g].m.B : sb;
-  const size_t lds = (size_t)sb * 32;
-  if (precision == 0)
+  // FP64 steps: 8 doubles per bin; FP32C steps: 3 + 8 floats per bin (the
+  // limiter factors are only used by FP64 steps)
+  const bool f64 = precision == 0 || a.pending_only;
+  const size_t lds = (size_t)sb * (f64 ? 8 * sizeof(double) : 12 * sizeof(float));
+  if (f64)
     hipLaunchKernelGGL(wave_step<false>, dim3(blocks), dim3(kWave), lds, st,
                        a);
   else
     hipLaunchKernelGGL(wave_step<true>, dim3(blocks), dim3(kWave), lds, st,
                        a);
-  return hipGetLastError();
-}
-
-hipError_t launch_wave_slow(const WaveArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(wave_slow, dim3(kSlowThreads / 64), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
