@@ -31,7 +31,9 @@ constexpr int kCompactBlock = 256;
 constexpr double kDefaultX1 = 3.3510321638291124e-11;  // 2 um water drop
 constexpr double kHitTol = 1e-12;
 constexpr int kDefaultSteps = 10;
-constexpr int kDefaultWaveBlocks = 2048;
+// persistent blocks of the wave kernel: enough one-wave blocks to fill every
+// SIMD several times over (256 CUs x 4 SIMDs x 8 waves)
+constexpr int kDefaultWaveBlocks = 8192;
 
 // Arguments a captured graph depends on.
 struct GraphKey {
@@ -150,6 +152,7 @@ void write_tune_cache(fsbm_coal_t h) {
 struct WaveTables {
   std::vector<short> own;
   int rows_g = 0, rows_l = 0;
+  std::vector<int> blk;  // [npairs][4]: gain rows offset, count; loss same
   std::vector<uint2> idx;
   std::vector<float2> x32, c32, k32;
   std::vector<double2> x64, k64;
@@ -207,17 +210,35 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
     wt.own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
     load[best] += wgt[q];
   }
-  // stream lengths per lane
-  std::vector<int> len_g(kWave, 0), len_l(kWave, 0);
+  // per lane and species pair (a <= b): the entries of its bins, in owned
+  // bin order; a block of rows per species pair, padded to its longest lane
+  const int npairs = S * (S + 1) / 2;
+  auto pair_of = [&](const Pair &pr) {
+    return pr.a * S - (pr.a * (pr.a - 1)) / 2 + (pr.b - pr.a);
+  };
+  std::vector<std::vector<std::vector<Pair>>> gl(
+      kWave, std::vector<std::vector<Pair>>(npairs)),
+      ll(kWave, std::vector<std::vector<Pair>>(npairs));
   for (int l = 0; l < kWave; ++l)
     for (int o = 0; o < kMaxOwn; ++o) {
       const int q = wt.own[(size_t)l * kMaxOwn + o];
       if (q < 0) continue;
-      len_g[l] += (int)T[q].size();
-      len_l[l] += (int)Lq[q].size();
+      for (const Pair &pr : T[q]) gl[l][pair_of(pr)].push_back(pr);
+      for (const Pair &pr : Lq[q]) ll[l][pair_of(pr)].push_back(pr);
     }
-  wt.rows_g = *std::max_element(len_g.begin(), len_g.end());
-  wt.rows_l = *std::max_element(len_l.begin(), len_l.end());
+  wt.blk.assign((size_t)npairs * 4, 0);
+  int rows = 0;
+  for (int side = 0; side < 2; ++side)
+    for (int ab = 0; ab < npairs; ++ab) {
+      int len = 0;
+      for (int l = 0; l < kWave; ++l)
+        len = std::max(len, (int)(side ? ll : gl)[l][ab].size());
+      wt.blk[(size_t)ab * 4 + 2 * side] = rows;
+      wt.blk[(size_t)ab * 4 + 2 * side + 1] = len;
+      rows += len;
+      if (side == 0) wt.rows_g += len;
+      else wt.rows_l += len;
+    }
   const size_t n = (size_t)(wt.rows_g + wt.rows_l) * kWave;
   wt.idx.assign(n, make_uint2(0u, 0u));
   wt.x32.assign(n, make_float2(0.f, 0.f));
@@ -244,24 +265,22 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
     // FP32 Courant number and its product with ln 2 as the kernels round it
     wt.c32[pos] = make_float2(ctf[ij], ctf[ij] * kLn2f);
     wt.c64[pos] = h->ct[ij];
-    const int ab = pr.a * S - (pr.a * (pr.a - 1)) / 2 + (pr.b - pr.a);
+    const int ab = pair_of(pr);
     for (int br = 0; br < nbr; ++br) {
       const size_t t = (((size_t)ab * nbr + br) * B * B + ij) * 2;
       wt.k32[(size_t)br * n + pos] = make_float2(Kf[t], Kf[t + 1]);
       wt.k64[(size_t)br * n + pos] = make_double2(Kd[t], Kd[t + 1]);
     }
   };
-  for (int l = 0; l < kWave; ++l) {
-    int rg = 0, rl = 0;
-    for (int o = 0; o < kMaxOwn; ++o) {
-      const int q = wt.own[(size_t)l * kMaxOwn + o];
-      if (q < 0) continue;
-      for (const Pair &pr : T[q])
-        put((size_t)(rg++) * kWave + l, pr, false);
-      for (const Pair &pr : Lq[q])
-        put((size_t)(wt.rows_g + rl++) * kWave + l, pr, true);
+  for (int l = 0; l < kWave; ++l)
+    for (int ab = 0; ab < npairs; ++ab) {
+      for (size_t e = 0; e < gl[l][ab].size(); ++e)
+        put((size_t)(wt.blk[(size_t)ab * 4] + e) * kWave + l, gl[l][ab][e],
+            false);
+      for (size_t e = 0; e < ll[l][ab].size(); ++e)
+        put((size_t)(wt.blk[(size_t)ab * 4 + 2] + e) * kWave + l,
+            ll[l][ab][e], true);
     }
-  }
   return FSBM_OK;
 }
 
@@ -373,6 +392,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       {wt.c64.data(), sizeof(double) * wt.c64.size(), 0},
       {wt.k32.data(), sizeof(float2) * wt.k32.size(), 0},
       {wt.k64.data(), sizeof(double2) * wt.k64.size(), 0},
+      {wt.blk.data(), sizeof(int) * wt.blk.size(), 0},
   };
   size_t off = 0;
   for (auto &p : parts) {
@@ -419,6 +439,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.we_c64 = (const double *)at(20);
   m.we_k32 = (const float2 *)at(21);
   m.we_k64 = (const double2 *)at(22);
+  m.wblk = (const int *)at(23);
   return FSBM_OK;
 }
 
@@ -924,7 +945,7 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
       for (int wpb : {1, 2}) cands.push_back({spl, wpb, 0});
   } else {
     for (int spl : {5, 10, 20})
-      for (int blocks : {1024, 2048, 4096, 8192})
+      for (int blocks : {2048, 4096, 8192, 16384})
         cands.push_back({spl, 1, blocks});
   }
   const int save_flags = h->flags;

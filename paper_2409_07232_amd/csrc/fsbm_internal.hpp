@@ -50,11 +50,12 @@ struct DevModel {
   // padded) and, per lane, a stream of gain entries (the pairs landing in
   // its bins) and a stream of loss entries (the pairs its bins lose mass
   // to), each entry holding the pair's static data.  Streams are
-  // interleaved by lane (entry r of lane l at r * 64 + l) and padded to the
-  // longest lane: rows [0, wrows_g) are gains, [wrows_g, wrows_g + wrows_l)
-  // losses.  A bin's entries are contiguous in its owner's stream.
+  // interleaved by lane (entry r of lane l at r * 64 + l) and cut into one
+  // block of rows per species pair (a <= b), padded to the block's longest
+  // lane: gain blocks first (wrows_g rows), then loss blocks (wrows_l).
   const short *own;
   int wrows_g, wrows_l;
+  const int *wblk;        // [npairs][4]: gain block row, rows; loss same
   const uint2 *we_idx;    // .x = qa | qb << 16, .y = q_target | flags << 16
   const float2 *we_x32;   // (x_i, x_j) FP32
   const double2 *we_x64;  // (x_i, x_j)

@@ -135,8 +135,9 @@ struct PassLds;
 template <>
 struct PassLds<false> {
   double *gain, *fout, *loss, *dneg;
-  __device__ void store(double *arr, int q, const AccF64 &a) const {
-    arr[q] = a.v;
+  // a bin's entries of one species-pair block, added to its sum
+  __device__ void merge(double *arr, int q, const AccF64 &a) const {
+    arr[q] += a.v;
   }
   __device__ double read(const double *arr, int q) const { return arr[q]; }
 };
@@ -144,9 +145,14 @@ template <>
 struct PassLds<true> {
   float *gain, *fout, *loss, *dneg;  // each [2][SB]: sums then compensations
   int SB;
-  __device__ void store(float *arr, int q, const AccF32 &a) const {
-    arr[q] = a.s;
-    arr[SB + q] = a.c;
+  __device__ void merge(float *arr, int q, const AccF32 &a) const {
+    AccF32 t;
+    t.s = arr[q];
+    t.c = arr[SB + q];
+    t.add(a.s);
+    t.c += a.c;
+    arr[q] = t.s;
+    arr[SB + q] = t.c;
   }
   __device__ double read(const float *arr, int q) const {
     return (double)arr[q] + (double)arr[SB + q];
@@ -173,7 +179,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   typedef typename std::conditional<F32, float, double>::type Real;
   typedef typename std::conditional<F32, float2, double2>::type Real2;
   const int lane = threadIdx.x;
-  const int B = m.B, SB = m.S * m.B;
+  const int B = m.B, S = m.S, SB = m.S * m.B;
   // LDS (8 SB doubles): masses, numbers, log-masses, then the pass sums and
   // the limiter factors
   Real *mass = (Real *)lds;
@@ -206,12 +212,14 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   const double Mtot = wave_sum_f64(part);
   const double thr = m.theta * Mtot;
   const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
+  uint64_t pres = 0;  // species with an active bin owned by this lane
 #pragma unroll
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
     const double Mq = st[q] * m.x[q % B];
     const bool act = Mq > 0.0 && Mq >= thr;
+    if (act) pres |= 1ull << (q / B);
     const double Mt = act ? Mq : 0.0;
     if constexpr (F32) {
       const float mq = (float)(Mt * inv);
@@ -235,6 +243,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     }
   }
   __syncthreads();
+  // species present at this point: pairs of absent species are skipped
+  // block by block (wave-uniform)
+  pres = wave_or64(pres);
   Real wr, tdt;
   if constexpr (F32) {
     wr = (float)w;
@@ -256,131 +267,138 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
 
   bool lim = false;
   for (int pass = 0; pass < 2; ++pass) {
-    // S3/S4 gains over this lane's gain stream
-    {
-      Acc g, f, d;
-      g.zero();
-      f.zero();
-      d.zero();
-      int cur = -1;
+    // S3/S4 gains over this lane's gain stream, species pair by pair
+    for (int sa = 0, ab = 0; sa < S; ++sa)
+      for (int sb = sa; sb < S; ++sb, ++ab) {
+        if (!((pres >> sa) & (pres >> sb) & 1ull)) continue;
+        const int r0 = m.wblk[ab * 4], r1 = r0 + m.wblk[ab * 4 + 1];
+        Acc g, f, d;
+        g.zero();
+        f.zero();
+        d.zero();
+        int cur = -1;
 #pragma unroll 2
-      for (int r = 0; r < m.wrows_g; ++r) {
-        const size_t pos = (size_t)r * kWave + lane;
-        const uint2 id = m.we_idx[pos];
-        const unsigned fl = id.y >> 16;
-        if (!(fl & kWValid)) continue;  // padding at the stream's end
-        const int qt = (int)(id.y & 0xffffu);
-        if (qt != cur) {
-          if (cur >= 0) {
-            P.store(P.gain, cur, g);
-            P.store(P.fout, cur, f);
-            if (pass == 0) P.store(P.dneg, cur, d);
+        for (int r = r0; r < r1; ++r) {
+          const size_t pos = (size_t)r * kWave + lane;
+          const uint2 id = m.we_idx[pos];
+          const unsigned fl = id.y >> 16;
+          if (!(fl & kWValid)) continue;  // padding at the block's end
+          const int qt = (int)(id.y & 0xffffu);
+          if (qt != cur) {
+            if (cur >= 0) {
+              P.merge(P.gain, cur, g);
+              P.merge(P.fout, cur, f);
+              if (pass == 0) P.merge(P.dneg, cur, d);
+            }
+            cur = qt;
+            g.zero();
+            f.zero();
+            d.zero();
           }
-          cur = qt;
-          g.zero();
-          f.zero();
-          d.zero();
-        }
-        const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
-        if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
-        const Real2 kk = ke[pos];
-        Real A, Bm;
-        entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb,
-                      (fl & kWSelf) != 0, xe[pos], A, Bm);
-        Real F;
-        if constexpr (F32)
-          F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c32[pos],
-                         A + Bm);
-        else
-          F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c64[pos],
-                         A + Bm);
-        const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-        if (pass == 1) {
-          const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A, Bm,
-                                     F);
-          A *= sc;
-          Bm *= sc;
-          F *= sc;
-        }
-        if constexpr (F32) {
-          // exact transfers: the same rounded amounts as the source side
-          if (!ta) g.add(A);
-          if (!tb) g.add(Bm);
-          g.add(-F);
-        } else {
-          // the pair's combined contribution to its target in one rounding
-          // (a target that is also a source keeps the other source's mass)
-          const double keep = ta ? Bm : (tb ? A : A + Bm);
-          g.add(keep - F);
-        }
-        f.add(F);
-        if (pass == 0) {
-          if (ta || tb) {
-            const Real keep = ta ? Bm : A;
-            if (F > keep) d.add(F - keep);
+          const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
+          if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
+          const Real2 kk = ke[pos];
+          Real A, Bm;
+          entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb,
+                        (fl & kWSelf) != 0, xe[pos], A, Bm);
+          Real F;
+          if constexpr (F32)
+            F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c32[pos],
+                           A + Bm);
+          else
+            F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c64[pos],
+                           A + Bm);
+          const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+          if (pass == 1) {
+            const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
+                                       Bm, F);
+            A *= sc;
+            Bm *= sc;
+            F *= sc;
           }
-          ++npairs;
+          if constexpr (F32) {
+            // exact transfers: the same rounded amounts as the source side
+            if (!ta) g.add(A);
+            if (!tb) g.add(Bm);
+            g.add(-F);
+          } else {
+            // the pair's combined contribution to its target in one
+            // rounding (a target that is also a source keeps the other
+            // source's mass)
+            const double keep = ta ? Bm : (tb ? A : A + Bm);
+            g.add(keep - F);
+          }
+          f.add(F);
+          if (pass == 0) {
+            if (ta || tb) {
+              const Real keep = ta ? Bm : A;
+              if (F > keep) d.add(F - keep);
+            }
+            ++npairs;
+          }
+        }
+        if (cur >= 0) {
+          P.merge(P.gain, cur, g);
+          P.merge(P.fout, cur, f);
+          if (pass == 0) P.merge(P.dneg, cur, d);
         }
       }
-      if (cur >= 0) {
-        P.store(P.gain, cur, g);
-        P.store(P.fout, cur, f);
-        if (pass == 0) P.store(P.dneg, cur, d);
-      }
-    }
     // losses over this lane's loss stream: the same collided amounts, seen
     // from the source bins
-    {
-      Acc lo;
-      lo.zero();
-      int cur = -1;
+    for (int sa = 0, ab = 0; sa < S; ++sa)
+      for (int sb = sa; sb < S; ++sb, ++ab) {
+        if (!((pres >> sa) & (pres >> sb) & 1ull)) continue;
+        const int r0 = m.wblk[ab * 4 + 2], r1 = r0 + m.wblk[ab * 4 + 3];
+        Acc lo;
+        lo.zero();
+        int cur = -1;
 #pragma unroll 2
-      for (int r = m.wrows_g; r < m.wrows_g + m.wrows_l; ++r) {
-        const size_t pos = (size_t)r * kWave + lane;
-        const uint2 id = m.we_idx[pos];
-        const unsigned fl = id.y >> 16;
-        if (!(fl & kWValid)) continue;
-        const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
-        const bool sideb = (fl & kWSideB) != 0;
-        const int q = sideb ? qb : qa;
-        if (q != cur) {
-          if (cur >= 0) P.store(P.loss, cur, lo);
-          cur = q;
-          lo.zero();
-        }
-        if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
-        const Real2 kk = ke[pos];
-        const bool self = (fl & kWSelf) != 0;
-        Real A, Bm;
-        entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb, self, xe[pos], A,
-                      Bm);
-        if (pass == 1) {
-          // the pair's scale, as its target's owner computes it
-          const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-          const int qt = (int)(id.y & 0xffffu);
-          Real F = (Real)0;
-          if (ta || tb) {
-            if constexpr (F32)
-              F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
-                             m.we_c32[pos], A + Bm);
-            else
-              F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
-                             m.we_c64[pos], A + Bm);
+        for (int r = r0; r < r1; ++r) {
+          const size_t pos = (size_t)r * kWave + lane;
+          const uint2 id = m.we_idx[pos];
+          const unsigned fl = id.y >> 16;
+          if (!(fl & kWValid)) continue;
+          const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
+          const bool sideb = (fl & kWSideB) != 0;
+          const int q = sideb ? qb : qa;
+          if (q != cur) {
+            if (cur >= 0) P.merge(P.loss, cur, lo);
+            cur = q;
+            lo.zero();
           }
-          const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A, Bm,
-                                     F);
-          A *= sc;
-          Bm *= sc;
+          if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
+          const Real2 kk = ke[pos];
+          const bool self = (fl & kWSelf) != 0;
+          Real A, Bm;
+          entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb, self, xe[pos],
+                        A, Bm);
+          if (pass == 1) {
+            // the pair's scale, as its target's owner computes it
+            const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+            const int qt = (int)(id.y & 0xffffu);
+            Real F = (Real)0;
+            if (ta || tb) {
+              if constexpr (F32)
+                F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
+                               m.we_c32[pos], A + Bm);
+              else
+                F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
+                               m.we_c64[pos], A + Bm);
+            }
+            const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
+                                       Bm, F);
+            A *= sc;
+            Bm *= sc;
+          }
+          if (self) {
+            lo.add(A);
+            lo.add(Bm);
+          } else {
+            lo.add(sideb ? Bm : A);
+          }
         }
-        if (self) {
-          lo.add(A);
-          lo.add(Bm);
-        } else {
-          lo.add(sideb ? Bm : A);
-        }
+        if (cur >= 0) P.merge(P.loss, cur, lo);
       }
-      if (cur >= 0) P.store(P.loss, cur, lo);
-    }
     // every pass sum and outgoing flux visible to all lanes
     __syncthreads();
     if (pass == 1) break;
@@ -399,8 +417,18 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     }
     lim = __any(over);
     if (!lim) break;
+    if constexpr (F32) {
+      __syncthreads();  // LDS is rewritten by the next step
+      return 2u;
+    }
+    // the second pass sums start from zero again
+#pragma unroll
+    for (int o = 0; o < kMaxOwn; ++o) {
+      const int q = own[o];
+      if (q < 0) continue;
+      P.gain[q] = P.fout[q] = P.loss[q] = (Real)0;
+    }
     __syncthreads();  // sigma visible before the second pass
-    if constexpr (F32) return 2u;
   }
 
   // S6: FP64 update of the owned bins
