@@ -133,6 +133,15 @@ __device__ __forceinline__ void comp_add_pos(float &s, float &c, float x) {
   s = t;
 }
 
+// log2 of x >= 0 split into an exact integer exponent e and the log2 of the
+// mantissa in [1/2, 1) (f in [-1, 0)): a difference of two such logs is
+// exact in its integer part, so it keeps ~1e-7 absolute accuracy where
+// |log2 x| is large (a plain FP32 log2 of 1e-9 is only good to ~2e-6).
+__device__ __forceinline__ void log2_split(float x, int &e, float &f) {
+  e = __builtin_amdgcn_frexp_expf(x);
+  f = __builtin_amdgcn_logf(__builtin_amdgcn_frexp_mantf(x));
+}
+
 // ------------------------------------------------------- flux fraction
 // f(c, x1) = integral over [1/2 - c, 1/2] of exp(x1 t) dt, clamped to
 // [0, 1]: the fraction of the merged mass that an exponential sub-bin

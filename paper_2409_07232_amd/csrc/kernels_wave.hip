@@ -46,6 +46,10 @@ namespace fsbm {
 
 namespace {
 
+// FP32C steps run only while no bin loses more than this fraction of its
+// mass in the step (see the S5 check in point_step)
+constexpr double kDrainFp32 = 0.5;
+
 struct AccF64 {
   double v;
   __device__ __forceinline__ void zero() { v = 0.0; }
@@ -104,12 +108,17 @@ __device__ __forceinline__ double entry_flux(bool has_flux, const double *Mt,
   return flux_fraction_f64(c, x1) * Sm;
 }
 
+// FP32: the base-2 log-slope from split logs (exponents exact), lm the
+// mantissa logs and le the exponents of the bin masses.
 __device__ __forceinline__ float entry_flux(bool has_flux, const float *m,
-                                            const float *lm, int qt,
-                                            float2 c, float Sm) {
+                                            const float *lm, const int *le,
+                                            int qt, float2 c, float Sm) {
   if (!has_flux) return 0.0f;
   const float den = __builtin_fmaxf(m[qt] + Sm, 0x1p-120f);
-  float lam = lm[qt + 1] - __builtin_amdgcn_logf(den);
+  int ed;
+  float fd;
+  log2_split(den, ed, fd);
+  float lam = (float)(le[qt + 1] - ed) + (lm[qt + 1] - fd);
   lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
   return flux_fraction_f32(c.x, c.y, lam) * Sm;
 }
@@ -200,6 +209,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     P.dneg = acc0 + 3 * SB;
   }
   double *sg = (double *)(lds + (size_t)7 * SB * sizeof(double));
+  // FP32 mode: exponents of the split mass logs, after the pass sums
+  int *lne = (int *)(acc0 + 8 * SB);
 
   // S1/S2: owned bins, FP64 total, activity (a bin's mass is recomputed
   // from its state where needed rather than kept in registers)
@@ -225,7 +236,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
       const float mq = (float)(Mt * inv);
       mass[q] = mq;
       nv[q] = (float)((act ? st[q] : 0.0) * inv);
-      lnm[q] = __builtin_amdgcn_logf(mq);
+      log2_split(mq, lne[q], lnm[q]);
     } else {
       mass[q] = Mt;
       nv[q] = act ? st[q] : 0.0;
@@ -303,7 +314,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
                         (fl & kWSelf) != 0, xe[pos], A, Bm);
           Real F;
           if constexpr (F32)
-            F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c32[pos],
+            F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt, m.we_c32[pos],
                            A + Bm);
           else
             F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c64[pos],
@@ -379,7 +390,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             Real F = (Real)0;
             if (ta || tb) {
               if constexpr (F32)
-                F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
+                F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt,
                                m.we_c32[pos], A + Bm);
               else
                 F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
@@ -403,7 +414,11 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     __syncthreads();
     if (pass == 1) break;
     // S5: demand of each owned bin = its negative merged nets; sigma where
-    // the demand exceeds the mass
+    // the demand exceeds the mass.  FP32C also leaves the step to FP64 mode
+    // when a bin would lose more than kDrainFp32 of its mass: the remainder
+    // M - D of a draining bin is then small against D, and FP32 amounts
+    // (inputs and arithmetic good to ~1e-7 of D) would carry a relative
+    // error of ~1e-7 D / (M - D) into it, step after step.
     bool over = false;
 #pragma unroll
     for (int o = 0; o < kMaxOwn; ++o) {
@@ -411,7 +426,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
       if (q < 0) continue;
       const double Mq = (double)mass[q];
       const double D = P.read(P.loss, q) + P.read(P.dneg, q);
-      const bool od = D > Mq;
+      const bool od = F32 ? (D > kDrainFp32 * Mq) : (D > Mq);
       over = over || od;
       if constexpr (!F32) sg[q] = od ? Mq / D : 1.0;
     }

@@ -65,6 +65,17 @@ def test_four_species(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_four_species_long(precision):
+    """100 steps: snow and graupel bins that drain most of their mass each
+    step (the FP32C path hands such steps to FP64 mode) and limiter steps."""
+    w = wl.config3(npoints=2048, nsteps=100).subset(np.arange(0, 2048, 2))
+    ref, x, lim = run_oracle(w)
+    got, st, _ = gpu_run(w, precision)
+    assert st["limiter_steps"] > 0 and lim.sum() > 0
+    check(got, ref, w.N, x, precision, "four-species-100", limited=lim)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("nbins,npts,nsteps", [(66, 70, 10), (132, 9, 5),
                                                (264, 3, 3)])
 def test_refined_grids(precision, nbins, npts, nsteps):
