@@ -104,6 +104,7 @@ class OracleModel:
     x1_g: float = 3.3510321638291124e-11
     s: int = 1
     theta: float = 1e-30
+    order: int = 0               # 0 simultaneous, 1 sequential (S == 1)
 
     def __post_init__(self):
         self.tables = np.ascontiguousarray(self.tables, dtype=np.float64)
@@ -113,7 +114,8 @@ class OracleModel:
         self._desc = _Desc(
             self.nbins, self.nspecies, self.nlevels, self.s, self.x1_g,
             self.theta, _dptr(self.tables), _dptr(self.p_levels),
-            self.product.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0)
+            self.product.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            int(self.order))
 
     def grid(self) -> np.ndarray:
         x = np.empty(self.nbins)
@@ -157,7 +159,11 @@ class OracleModel:
             int(nthreads))
         if rc:
             raise ValueError("oracle rejected its input")
-        res = {"limiter_steps": int(lim.value), "limiter_per_point": lim_pt}
+        if self.order == 1:
+            res = {"capped_pairs": int(lim.value), "capped_per_point": lim_pt}
+        else:
+            res = {"limiter_steps": int(lim.value),
+                   "limiter_per_point": lim_pt}
         if totals:
             res.update({"mass_before": outs[0], "mass_after": outs[1],
                         "num_before": outs[2], "num_after": outs[3]})

@@ -56,8 +56,10 @@ static int species_pair_index(int S, int a, int b) {
 static int check_desc(const fsbm_oracle_desc *d) {
   if (!d || d->nbins < 2 || d->nspecies < 1 || d->nspecies > 8 ||
       d->nlevels < 1 || d->s < 1 || !(d->x1_g > 0.0) || !d->tables ||
-      !d->p_levels || !d->product || d->order != 0 || !(d->theta >= 0.0))
+      !d->p_levels || !d->product || d->order < 0 || d->order > 1 ||
+      !(d->theta >= 0.0))
     return -1;
+  if (d->order == 1 && d->nspecies != 1) return -1; /* [R16]: one species */
   for (int l = 0; l + 1 < d->nlevels; ++l)
     if (!(d->p_levels[l] > d->p_levels[l + 1])) return -1;
   for (int a = 0; a < d->nspecies; ++a)
@@ -335,6 +337,96 @@ static int step_point(const ctx_t *cx, double *N, double p, double dt,
   return limited;
 }
 
+/* One time step of one point in Bott's original, sequential form [R16]
+   (one species): the pairs are taken one after another in the canonical
+   order (i ascending, then j = i..B-1 ascending) and each pair moves mass
+   in place, so a pair sees every change made by the pairs before it.
+   Per pair (i, j) whose bins are both active with their current masses:
+     C  = dt K_ij(p) N_i N_j  (1/2 of it when i == j)     collisions per cm^3
+     A  = C x_i leaves bin i, Bm = C x_j leaves bin j, Sm = A + Bm merges
+     into bin k = k_ij, and the flux F = f(c_ij, x1) Sm moves on to k+1 with
+     x1 = ln(M_{k+1} / M_k'), M_k' the content of bin k after the removals
+     and the merge (the profile of the simultaneous form [R3, R4]).
+   Positivity without a second pass, by caps on the bins that lose mass:
+     C <= N_i (C <= N_i / 2 when i == j): bin i gives at most what it holds;
+     C <= N_j when the merged mass does not land in bin j (when it does, the
+     collector bin keeps its particles, which may collide many times);
+     F <= M_k': the flux moves at most what bin k then holds.
+   Returns the number of pairs at which a cap applied. */
+static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
+                          double *M) {
+  const int B = cx->B;
+  const double *x = cx->x;
+  double Mtot = 0.0;
+  for (int q = 0; q < B; ++q) {
+    M[q] = N[q] * x[q];
+    Mtot += M[q];
+  }
+  if (Mtot == 0.0) return 0;
+  /* activity [R8] with the current masses against the step's total */
+  const double thr = cx->d->theta * Mtot;
+  int l;
+  double w;
+  pressure_bracket(cx->d, p, &l, &w);
+  int capped = 0;
+  for (int i = 0; i < B; ++i)
+    for (int j = i; j < B; ++j) {
+      if (!(M[i] > 0.0 && M[i] >= thr && M[j] > 0.0 && M[j] >= thr))
+        continue;
+      const int k = cx->kt[i * B + j];
+      if (k < 0) continue; /* [R6] */
+      const double K = kernel_entry(cx->d, 0, l, w, i, j);
+      const double Ni = M[i] / x[i], Nj = M[j] / x[j];
+      double C = dt * K * Ni * Nj;
+      double cap = Ni;
+      if (i == j) {
+        C *= 0.5; /* [R7] */
+        cap = 0.5 * Ni;
+      } else if (k != j && Nj < cap) {
+        cap = Nj;
+      }
+      int hit = 0;
+      if (C > cap) {
+        C = cap;
+        hit = 1;
+      }
+      if (C == 0.0) continue;
+      const double A = C * x[i], Bm = C * x[j], Sm = A + Bm;
+      /* removals; the target's content after them and the merged mass.  When
+         the target is the partner bin j, its content is formed as M_j + A
+         (the same value as (M_j - Bm) + Sm without the rounding of the large
+         Bm twice). */
+      double Mk;
+      if (i == j) {
+        M[i] -= Sm;
+        Mk = M[k] + Sm;
+      } else if (k == j) {
+        M[i] -= A;
+        Mk = M[j] + A;
+      } else {
+        M[i] -= A;
+        M[j] -= Bm;
+        Mk = M[k] + Sm;
+      }
+      double F = 0.0;
+      if (k <= B - 2) {
+        double x1 = log(M[k + 1] / Mk);
+        if (!(x1 >= X1_FLOOR)) x1 = X1_FLOOR; /* [R4]; also log(0) */
+        F = fsbm_oracle_flux_fraction(cx->ct[i * B + j], x1) * Sm;
+        if (F > Mk) {
+          F = Mk;
+          hit = 1;
+        }
+        M[k + 1] += F;
+      }
+      M[k] = Mk - F;
+      capped += hit;
+    }
+  /* back to numbers; negative round-off clamped as in S6 */
+  for (int q = 0; q < B; ++q) N[q] = (M[q] < 0.0 ? 0.0 : M[q]) / x[q];
+  return capped;
+}
+
 static void point_totals(const ctx_t *cx, const double *N, double *m,
                          double *num) {
   const int B = cx->B, n = cx->S * B;
@@ -430,7 +522,8 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
         if (num_before) num_before[pt] = n0;
         int32_t lim_pt = 0;
         for (int st = 0; st < nsteps; ++st)
-          lim_pt += step_point(&cx, Np, p[pt], dt, &wk);
+          lim_pt += d->order == 1 ? step_point_seq(&cx, Np, p[pt], dt, wk.M)
+                                  : step_point(&cx, Np, p[pt], dt, &wk);
         lim_total += lim_pt;
         if (limiter_per_point) limiter_per_point[pt] = lim_pt;
         if (mass_after || num_after) {

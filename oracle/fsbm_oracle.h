@@ -42,14 +42,18 @@ typedef struct {
                                [i][j] = species a bin i with species b bin j */
   const double *p_levels;   /* [L], hPa, strictly decreasing */
   const int32_t *product;   /* [S*S] product species of (a,b), symmetric */
-  int32_t order;            /* 0 = simultaneous update (the only mode) */
+  int32_t order;            /* 0 = simultaneous update of every pair from
+                               the step's start state (S1-S6);
+                               1 = Bott's sequential in-place update, one
+                               species only (no limiter: a per-pair cap) */
 } fsbm_oracle_desc;
 
 /* Advance npoints independent points by nsteps steps of dt, in place.
  * N: host [npoints][S][B].  p: host [npoints].  Optional outputs (may be
  * NULL): per-point total mass / number before the first and after the last
  * step, the number of point-steps in which the limiter fired, and per point
- * the number of its steps in which it fired.
+ * the number of its steps in which it fired.  With order == 1 the last two
+ * count capped pairs instead (summed over all pairs and steps).
  * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad input. */
 int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t npoints, double dt, int32_t nsteps,
