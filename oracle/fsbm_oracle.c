@@ -352,7 +352,11 @@ static int step_point(const ctx_t *cx, double *N, double p, double dt,
      C <= N_j when the merged mass does not land in bin j (when it does, the
      collector bin keeps its particles, which may collide many times);
      F <= M_k': the flux moves at most what bin k then holds.
-   Returns the number of pairs at which a cap applied. */
+   A bin whose cap applied is left with exactly nothing, the value of
+   M - (M / x) x in exact arithmetic: a rounding residue of either sign
+   would keep or drop the bin from the later pairs of the step, and a pair
+   (i, j) moves 2^(j-i) times bin i's mass in bin j, so residues would be
+   amplified by up to 2^(B-1).  Returns the number of capped pairs. */
 static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
                           double *M) {
   const int B = cx->B;
@@ -398,14 +402,14 @@ static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
          Bm twice). */
       double Mk;
       if (i == j) {
-        M[i] -= Sm;
+        M[i] = hit ? 0.0 : M[i] - Sm;
         Mk = M[k] + Sm;
       } else if (k == j) {
-        M[i] -= A;
+        M[i] = hit ? 0.0 : M[i] - A;
         Mk = M[j] + A;
       } else {
-        M[i] -= A;
-        M[j] -= Bm;
+        M[i] = hit && C == Ni ? 0.0 : M[i] - A;
+        M[j] = hit && C == Nj ? 0.0 : M[j] - Bm;
         Mk = M[k] + Sm;
       }
       double F = 0.0;
