@@ -35,8 +35,25 @@ extern "C" {
 
 /* arithmetic of the pair loop */
 #define FSBM_FP64 0  /* every step in FP64 */
-#define FSBM_FP32C 1 /* FP32 pair arithmetic with compensated per-bin sums,
-                        FP64 totals and FP64 final update */
+#define FSBM_FP32C 1 /* FP32 pair arithmetic (collided masses, flux
+                        fraction, transcendentals) on masses normalised by
+                        the point's FP64 total; the FP32 amounts are summed
+                        per bin in FP64 (each enters exactly, so a transfer
+                        leaves and enters with the same value); FP64 final
+                        update.  Steps that need the positivity limiter run
+                        in FP64. */
+
+/* update order of the pairs within a step */
+#define FSBM_ORDER_SIMULTANEOUS 0 /* every pair from the step's start state,
+                                     per-bin gain and loss sums, positivity
+                                     limiter when a bin is over-demanded */
+#define FSBM_ORDER_SEQUENTIAL 1   /* Bott's original in-place form: pairs in
+                                     order (i ascending, then j >= i), each
+                                     seeing the mass the pairs before it
+                                     moved; per-pair caps keep every bin
+                                     non-negative.  One species on the
+                                     doubling grid (s == 1), B in {3, 8, 16,
+                                     33, 40}, FSBM_FP64 only */
 
 /* option flags */
 #define FSBM_FLAG_DEBUG_CHECKS 1 /* validate N (>= 0, finite) before a step */
@@ -64,6 +81,10 @@ typedef struct {
   int32_t steps_per_launch; /* time steps fused into one kernel launch;
                                0 = choose (tuning cache or default) */
   int32_t flags;            /* FSBM_FLAG_* */
+  int32_t order;            /* FSBM_ORDER_SIMULTANEOUS (default) or
+                               FSBM_ORDER_SEQUENTIAL; a sequential handle
+                               outside the shapes above is FSBM_EUNSUPPORTED
+                               at create */
 } fsbm_coal_opts;
 
 /* Fill opts with the defaults above. */
@@ -113,7 +134,7 @@ int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
  * one work list and advanced by one persistent kernel per group of fused
  * steps.  Arrays are indexed by grid; same ownership rules as
  * fsbm_coal_step.  All handles must use the same precision and device, be
- * distinct, and have S*B <= 768; at most 4 grids.  Results equal those of
+ * distinct, have S*B <= 768 and the simultaneous order; at most 4 grids.  Results equal those of
  * fsbm_coal_step per grid with the one-point-per-wave kernel, bit for bit.
  * The pair, limiter and exact-path counters and the profiled launch
  * timings of the call are kept in the handle with the largest S*B (the
@@ -147,7 +168,9 @@ typedef struct {
   int64_t pair_evals;     /* bin pairs evaluated (both bins active, merged
                              mass inside the grid), summed over points and
                              steps of the last call */
-  int64_t limiter_steps;  /* point-steps where the positivity limiter ran */
+  int64_t limiter_steps;  /* point-steps where the positivity limiter ran;
+                             sequential order: pairs at which a positivity
+                             cap applied */
   int64_t fp64_fallback_steps; /* point-steps taken in FP64 outside the
                                   fast path: one point per lane, once the
                                   fast kernel finds that the limiter may
@@ -157,7 +180,8 @@ typedef struct {
                                   limiter fires the point takes that and
                                   every remaining step of the call in FP64
                                   mode */
-  int32_t kernel;         /* 0 = one point per lane, 1 = one point per wave */
+  int32_t kernel;         /* 0 = one point per lane, 1 = one point per
+                             wave, 2 = one point per lane, sequential */
   int32_t steps_per_launch;
   int32_t waves_per_block;
   int32_t kernel_launches; /* FSBM_FLAG_PROFILE: collision-kernel launches

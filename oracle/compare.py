@@ -60,3 +60,38 @@ def l1_point(N_cand, N_ref, x):
     d = np.abs(Mc - Mr).reshape(P, -1).sum(axis=1)
     ok = tot > 0
     return float(np.max(d[ok] / tot[ok])) if ok.any() else 0.0
+
+
+def per_point_rel_bin(N_cand, N_ref, x, floor=1e-9):
+    """rel_bin of each point separately ([P])."""
+    P = N_ref.shape[0]
+    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
+    return np.array([rel_bin(N_cand[q:q + 1], N_ref[q:q + 1], x,
+                             floor=fl[q:q + 1]) for q in range(P)])
+
+
+# Conditioning at FP32 precision: the activity threshold makes the step
+# discontinuous in the state, so where a bin of a point crosses it near a
+# step boundary the point's result jumps under rounding-sized changes of
+# the input.  Such a point is recognised by the oracle alone: its result
+# moves by more than tol under input noise of half an FP32 ulp.
+COND_AMP = 3e-8
+COND_SEEDS = (0, 1, 2)
+
+
+def unstable_points(model, N, p, dt, nsteps, ref, x, floor, tol,
+                    amp=COND_AMP, seeds=COND_SEEDS):
+    """model: an oracle.OracleModel; N, p: the points' inputs; ref: the
+    oracle's result for them; floor: per-point rel_bin floors.  True where
+    some seeded perturbation N (1 + amp z) moves the oracle's result by more
+    than tol (rel_bin against ref)."""
+    N = np.asarray(N, dtype=np.float64)
+    P = N.shape[0]
+    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
+    out = np.zeros(P, dtype=bool)
+    for seed in seeds:
+        z = np.random.default_rng(seed).standard_normal(N.shape)
+        Np = np.ascontiguousarray(N * (1.0 + amp * z))
+        model.run(Np, p, dt, nsteps)
+        out |= per_point_rel_bin(Np, ref, x, fl) > tol
+    return out

@@ -25,6 +25,8 @@ FSBM_EUNSUPPORTED = -4
 FSBM_EDOMAIN = -5
 FSBM_FP64 = 0
 FSBM_FP32C = 1
+ORDER_SIMULTANEOUS = 0
+ORDER_SEQUENTIAL = 1
 FLAG_DEBUG_CHECKS = 1
 FLAG_NO_GRAPH = 2
 FLAG_FORCE_WAVE = 4
@@ -53,7 +55,8 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32),
                 ("theta", ctypes.c_double),
                 ("steps_per_launch", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -153,7 +156,7 @@ class FsbmCoal:
                  p_levels, *, x1_g: Optional[float] = None, s: int = 1,
                  product=None, precision: int = FSBM_FP64,
                  theta: float = 1e-30, steps_per_launch: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, order: int = ORDER_SIMULTANEOUS):
         lib = load()
         self.nbins, self.nspecies = int(nbins), int(nspecies)
         self.precision = int(precision)
@@ -167,6 +170,7 @@ class FsbmCoal:
         opts.precision = self.precision
         opts.theta = float(theta)
         opts.steps_per_launch = int(steps_per_launch)
+        opts.order = int(order)
         opts.flags = int(flags)
         prod = None
         if product is not None:

@@ -1,6 +1,6 @@
 // device_common.hpp -- small device helpers shared by the gfx950 kernels of
 // the collision step: register-resident bin arrays with wave-uniform dynamic
-// indexing, wave reductions, compensated summation and the flux fraction.
+// indexing, wave reductions, the split log2 and the flux fraction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,49 +94,13 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(
   return v;
 }
 
-// ------------------------------------------------- compensated summation
-// Compensated sum in the Kahan family (Neumaier's form): the rounding error
-// of every addition is recovered exactly with Knuth's TwoSum and collected in
-// c, so s + c equals the exact sum of the inputs up to O(n u^2).  Plain
-// Kahan keeps only part of each error (up to ~2u of the running total per
-// step), which is too little for exact mass bookkeeping.
-__device__ __forceinline__ void comp_add(float &s, float &c, float x) {
-  const float t = s + x;
-  const float bp = t - s;
-  const float ap = t - bp;
-  const float e = (s - ap) + (x - bp);
-  c += e;
-  s = t;
-}
-
-// The same for a non-negative running sum and a non-negative term: with
-// the larger operand first, Dekker's Fast2Sum recovers the same exact
-// rounding error as TwoSum (identical s and c) in one operation less.
-__device__ __forceinline__ float vmax_f32(float a, float b) {
-  // plain v_max_f32: both operands are finite, so the NaN quieting the
-  // compiler adds around fmaxf is not needed
-  float r;
-  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ float vmin_f32(float a, float b) {
-  float r;
-  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ void comp_add_pos(float &s, float &c, float x) {
-  const float a = vmax_f32(s, x);
-  const float b = vmin_f32(s, x);
-  const float t = a + b;
-  const float e = b - (t - a);
-  c += e;
-  s = t;
-}
-
 // log2 of x >= 0 split into an exact integer exponent e and the log2 of the
 // mantissa in [1/2, 1) (f in [-1, 0)): a difference of two such logs is
 // exact in its integer part, so it keeps ~1e-7 absolute accuracy where
 // |log2 x| is large (a plain FP32 log2 of 1e-9 is only good to ~2e-6).
+// The hardware log2 rounds toward -infinity, so a plain difference of two
+// logs of different size carries a one-sided error of up to half an ulp
+// of the larger (4e-6 near log2 = -100); split, it is below 3e-8.
 __device__ __forceinline__ void log2_split(float x, int &e, float &f) {
   e = __builtin_amdgcn_frexp_expf(x);
   f = __builtin_amdgcn_logf(__builtin_amdgcn_frexp_mantf(x));
@@ -165,6 +129,11 @@ __device__ __forceinline__ double flux_fraction_f64(double c, double x1) {
 //   f = c 2^(lam/2) g(y),  y = c x1,  g(y) = (1 - e^-y) / y,
 // with g from its Taylor series for |y| < 1/4 (truncation error below
 // 5e-8) and from the hardware exp2 otherwise.  cl2 = c ln 2.
+// Errors here must be unbiased, not only small: the tail of a spectrum is
+// built over many steps from fluxes of this form, so a one-sided error of
+// 1e-7 in f adds up (measured: up to 2e-4 in bins holding 1e-9 of a
+// point's mass).  The hardware reciprocal of a negative y rounds toward
+// zero; one Newton step leaves a round-to-nearest error instead.
 __device__ __forceinline__ float flux_fraction_f32(float c, float cl2,
                                                    float lam) {
   const float y = cl2 * lam;
@@ -175,7 +144,9 @@ __device__ __forceinline__ float flux_fraction_f32(float c, float cl2,
                                                     y * (1.0f / 120.0f -
                                                          y * (1.0f / 720.0f)))));
   } else {
-    g = (1.0f - __builtin_amdgcn_exp2f(-c * lam)) * __builtin_amdgcn_rcpf(y);
+    float r = __builtin_amdgcn_rcpf(y);
+    r = __builtin_fmaf(r, __builtin_fmaf(-y, r, 1.0f), r);
+    g = (1.0f - __builtin_amdgcn_exp2f(-c * lam)) * r;
   }
   return __builtin_fminf(c * e * g, 1.0f);
 }

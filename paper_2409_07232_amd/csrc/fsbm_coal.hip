@@ -58,6 +58,7 @@ struct fsbm_coal_s {
   int B = 0, S = 0, L = 0, s = 1, precision = FSBM_FP64, flags = 0;
   int steps_per_launch = 0, waves_per_block = 0, wave_blocks = 0;
   bool lane = false;  // one-point-per-lane kernels apply
+  int order = FSBM_ORDER_SIMULTANEOUS;
   double x1 = kDefaultX1, theta = 1e-30;
   std::vector<double> x, ct;
   std::vector<int> kt, product;
@@ -113,6 +114,12 @@ bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 // Launch-shape cache: lines "B S precision kernel steps_per_launch
 // waves_per_block wave_blocks".
+// 0 one point per lane, 1 one point per wave, 2 sequential (per lane)
+int kernel_id(fsbm_coal_t h) {
+  if (h->order == FSBM_ORDER_SEQUENTIAL) return 2;
+  return h->lane ? 0 : 1;
+}
+
 void read_tune_cache(fsbm_coal_t h) {
   const char *path = getenv("FSBM_TUNE_CACHE");
   if (!path) return;
@@ -122,7 +129,7 @@ void read_tune_cache(fsbm_coal_t h) {
   while (fscanf(f, "%d %d %d %d %d %d %d", &B, &S, &pr, &kern, &spl, &wpb,
                 &wb) == 7) {
     if (B == h->B && S == h->S && pr == h->precision &&
-        kern == (h->lane ? 0 : 1) && spl > 0 && wpb >= 1 && wpb <= 2 &&
+        kern == kernel_id(h) && spl > 0 && wpb >= 1 && wpb <= 2 &&
         wb >= 0) {
       if (h->steps_per_launch == 0) h->steps_per_launch = spl;
       h->waves_per_block = wpb;
@@ -138,7 +145,7 @@ void write_tune_cache(fsbm_coal_t h) {
   FILE *f = fopen(path, "a");
   if (!f) return;
   fprintf(f, "%d %d %d %d %d %d %d\n", h->B, h->S, h->precision,
-          h->lane ? 0 : 1, h->steps_per_launch, h->waves_per_block,
+          kernel_id(h), h->steps_per_launch, h->waves_per_block,
           h->wave_blocks);
   fclose(f);
 }
@@ -635,7 +642,14 @@ int enqueue_call(const Call &c, hipStream_t st) {
       RC_TRY(event_pair(h0, &e0, &e1));
       HIP_TRY(h0, hipEventRecord(e0, st));
     }
-    if (!c.wave) {
+    if (!c.wave && h0->order == FSBM_ORDER_SEQUENTIAL) {
+      // in place: the state stays in the buffer it started from
+      la.nsteps = n;
+      la.steps_left = c.nsteps - done;
+      la.state = lane_cur;
+      la.state_alt = lane_alt;
+      HIP_TRY(h0, launch_lane_seq(la, c.wpb, h0->ws.slot_cap, st));
+    } else if (!c.wave) {
       la.nsteps = n;
       la.steps_left = c.nsteps - done;
       la.state = lane_cur;
@@ -647,13 +661,16 @@ int enqueue_call(const Call &c, hipStream_t st) {
       wa.nsteps = n;
       wa.steps_left = c.nsteps - done;
       HIP_TRY(h0, launch_wave_step(wa, h0->precision, c.blocks, st));
+      ++wa.launch_idx;
     }
     if (prof) HIP_TRY(h0, hipEventRecord(e1, st));
   }
   // points the fast kernels handed over finish the call on the exact path:
   // lane kernels, one lane per point (their state is valid in both lane
   // buffers); FP32C wave kernel, the FP64 wave kernel on those points
-  if (c.nsteps > 0 && !c.wave) {
+  if (c.nsteps > 0 && !c.wave && h0->order == FSBM_ORDER_SEQUENTIAL) {
+    // no hand-over: the sequential form stays positive by its caps
+  } else if (c.nsteps > 0 && !c.wave) {
     la.state = lane_cur;
     la.state_alt = lane_alt;
     HIP_TRY(h0, launch_slow_steps(la, h0->ws.slot_cap, st));
@@ -756,6 +773,7 @@ void fsbm_coal_opts_default(fsbm_coal_opts *o) {
   o->theta = 1e-30;
   o->steps_per_launch = 0;
   o->flags = 0;
+  o->order = FSBM_ORDER_SIMULTANEOUS;
 }
 
 int fsbm_coal_create(int32_t nbins, int32_t nspecies,
@@ -774,8 +792,13 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
   if (o.s < 1 || !finite_pos(o.x1_g) || !(o.theta >= 0.0) ||
       !isfinite(o.theta) ||
       (o.precision != FSBM_FP64 && o.precision != FSBM_FP32C) ||
-      o.steps_per_launch < 0)
+      o.steps_per_launch < 0 ||
+      (o.order != FSBM_ORDER_SIMULTANEOUS && o.order != FSBM_ORDER_SEQUENTIAL))
     return FSBM_EINVAL;
+  if (o.order == FSBM_ORDER_SEQUENTIAL &&
+      (!lane_kernel_supported(nbins, nspecies, o.s) ||
+       o.precision != FSBM_FP64 || (o.flags & FSBM_FLAG_FORCE_WAVE)))
+    return FSBM_EUNSUPPORTED;
   for (int l = 0; l < nlevels; ++l)
     if (!isfinite(p_levels_hpa[l])) return FSBM_EINVAL;
   for (int l = 0; l + 1 < nlevels; ++l)
@@ -815,6 +838,7 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
   h->product = product;
   h->lane = lane_kernel_supported(nbins, nspecies, o.s) &&
             !(o.flags & FSBM_FLAG_FORCE_WAVE);
+  h->order = o.order;
   read_tune_cache(h);
   const int rc = build_model(h, kernel_tables, p_levels_hpa);
   if (rc != FSBM_OK) {
@@ -862,6 +886,7 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
     if (hs[g]->precision != hs[0]->precision) return FSBM_EINVAL;
     if (hs[g]->device != hs[0]->device) return FSBM_EINVAL;
     if (hs[g]->S * hs[g]->B > kWave * kMaxOwn) return FSBM_EUNSUPPORTED;
+    if (hs[g]->order != FSBM_ORDER_SIMULTANEOUS) return FSBM_EUNSUPPORTED;
     for (int k = 0; k < g; ++k)
       if (hs[k] == hs[g]) return FSBM_EINVAL;  // one workspace per grid
     if (npoints[g] == 0) continue;
@@ -1031,7 +1056,7 @@ int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
 int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   if (!h || !out) return FSBM_EINVAL;
   memset(out, 0, sizeof(*out));
-  out->kernel = h->lane ? 0 : 1;
+  out->kernel = kernel_id(h);
   out->steps_per_launch = steps_per_launch(h);
   out->waves_per_block = h->lane ? waves_per_block(h) : 1;
   if (h->wpoints < 0) return FSBM_OK;

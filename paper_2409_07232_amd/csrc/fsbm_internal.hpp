@@ -112,7 +112,8 @@ struct DevWork {
   unsigned *keys;        // [slot_cap] sort keys (lane kernels) or null
   int *pending;          // [slot_cap] steps of the call left for the exact
                          // FP64 path (0 = point still on the fast path)
-  unsigned long long *counters;  // [4]: pair evals, limiter, fallback, -
+  unsigned long long *counters;  // [4]: pair evals, limiter, fallback,
+                                 // work-queue position of the wave kernel
 };
 
 // One grid of a one-point-per-wave launch (a call may cover several grids).
@@ -134,6 +135,7 @@ struct WaveArgs {
   int nsteps;       // steps in this launch
   int steps_left;   // steps of the call left when this launch starts
   int pending_only; // FP64 steps for the points marked pending only
+  int launch_idx;   // launches of this call before this one (work queue)
 };
 
 // Arguments of the step kernels.
@@ -197,6 +199,11 @@ hipError_t launch_lane_step(const StepArgs &a, int precision,
 // in the FP64 follow-up launch with pending_only set).
 hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
                             hipStream_t st);
+
+// One-point-per-lane kernel of the sequential (in-place) form: one species,
+// mass-doubling grid, FP64; updates the state in place (a.state).
+hipError_t launch_lane_seq(const StepArgs &a, int wpb, int max_slots,
+                           hipStream_t st);
 
 // Exact FP64 steps (with the positivity limiter) for every slot whose fast
 // kernel stopped on an over-demand bound: once a point leaves the fast path

@@ -27,9 +27,11 @@
 //  * FP64 kernel: the method as defined, in FP64.
 //  * FP32C kernel: masses normalised by the point's FP64 total; pair amounts
 //    in FP32, applied as exact transfers (bin i -> bin j: A, bin j -> bin
-//    j+1: F and the self-pair mass) into compensated per-bin sums (Kahan
-//    family, TwoSum error capture), then carried into an FP64 update of the
-//    FP64 state.
+//    j+1: F and the self-pair mass) into per-bin sums held in FP64, then
+//    carried into an FP64 update of the FP64 state.  Each FP32 amount
+//    enters its sums exactly; an FP64 add issues at the rate of an FP32 one
+//    on CDNA, so the widened sum (convert + add) costs a third of an FP32
+//    compensated one (max, min, add, sub, sub, add) and is more accurate.
 // A lane whose over-demand test fires leaves the fast kernel; the exact FP64
 // path (slow_path.hpp) takes the rest of the call's steps for it.
 #include <float.h>
@@ -37,8 +39,8 @@
 #include "device_common.hpp"
 #include "slow_path.hpp"
 
-// Kahan sums and the exact-transfer bookkeeping rely on every rounding
-// being the one written; fused forms are spelled out where wanted.
+// The exact-transfer bookkeeping relies on every rounding being the one
+// written; fused forms are spelled out where wanted.
 #pragma clang fp contract(off)
 
 namespace fsbm {
@@ -246,8 +248,8 @@ __global__ void __launch_bounds__(kWave *WPB)
 }
 
 // --------------------------------------------------------- FP32C kernel
-// Same sweep and double buffering as the FP64 kernel; the carried gain and
-// the losses are compensated FP32 sums, the update is FP64.
+// Same sweep and double buffering as the FP64 kernel; pair arithmetic in
+// FP32, the carried gain and the losses summed in FP64, the update FP64.
 template <int B, int WPB>
 __global__ void __launch_bounds__(kWave *WPB)
     __attribute__((amdgpu_waves_per_eu(B <= 33 ? 3 : 2))) lane_step_f32c(
@@ -290,8 +292,8 @@ __global__ void __launch_bounds__(kWave *WPB)
     const double thr = theta * Mtot;
     const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
     uint64_t act = 0;
-    BinsF<B> m;        // active M_k / M_tot
-    BinsF<B> Ls, Lc;   // compensated losses of bins as smaller partner
+    BinsF<B> m;  // active M_k / M_tot
+    BinsD<B> L;  // losses of bins as the smaller partner (FP64 sums)
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       const double v = sb[k * kWave + lane];
@@ -299,8 +301,7 @@ __global__ void __launch_bounds__(kWave *WPB)
       const bool ak = Mk > 0.0 && Mk >= thr;
       act |= (uint64_t)ak << k;
       m.set(k, ak ? (float)(Mk * inv) : 0.0f);
-      Ls.set(k, 0.0f);
-      Lc.set(k, 0.0f);
+      L.set(k, 0.0);
     }
     const float tau = (float)(dt * Mtot);
     const uint64_t uni = wave_or64(act);
@@ -310,12 +311,11 @@ __global__ void __launch_bounds__(kWave *WPB)
     const uint32_t uni_hi = uniform((int)(uint32_t)(uni >> 32));
     bool flag = false;
     unsigned step_pairs = 0;
-    // S6 for bin k: FP64 update from the FP64 gain g and the compensated
-    // losses, written to the other buffer
+    // S6 for bin k: FP64 update from the FP64 gain g and losses, written
+    // to the other buffer
     auto finish = [&](int k, double g, double Nk) {
-      const double l = (double)Ls.get(k) + (double)Lc.get(k);
       const double Mk = ldexp(__dmul_rn(Nk, x1), k);
-      double Mn = Mk + (g - l) * Mtot;
+      double Mn = Mk + (g - L.get(k)) * Mtot;
       Mn = Mn < 0.0 ? 0.0 : Mn;
       if (live) so[k * kWave + lane] = ldexp(Mn / x1, -k);
     };
@@ -330,8 +330,8 @@ __global__ void __launch_bounds__(kWave *WPB)
       Nnext = sb[j * kWave + lane];
       double gj = 0.0;  // gain of bin j from row j
       if (bit_of(uni_lo, uni_hi, j)) {
-        float fs = 0.0f, fc = 0.0f;  // flux leaving bin j for j+1
-        float self2 = 0.0f;          // self-pair mass, bin j -> j+1
+        double fs = 0.0;     // flux leaving bin j for j+1
+        float self2 = 0.0f;  // self-pair mass, bin j -> j+1
         const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
         const uint32_t cl = uni_lo & (uint32_t)below_mask;
         const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
@@ -344,11 +344,14 @@ __global__ void __launch_bounds__(kWave *WPB)
         // tj K = tj K_{l+1} + (tj w) (K_l - K_{l+1})
         const float tjw = tj * wf;
         const bool has_flux = j <= B - 2;
-        const float lmj1 =
-            has_flux ? __builtin_amdgcn_logf(m.get(j + 1)) : 0.0f;  // log2
+        // slope logs split into exact exponents and mantissa logs (see
+        // log2_split: the tail's masses are tiny and their logs large)
+        int ej1 = 0;
+        float fj1 = 0.0f;
+        if (has_flux) log2_split(m.get(j + 1), ej1, fj1);
         const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
         const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, c ln 2)
-        float as = 0.0f, ac = 0.0f;  // mass arriving in bin j
+        double as = 0.0;  // mass arriving in bin j
         // columns in chunks of 8: the chunk's table entries (kernel pair and
         // Courant pair per column) are fetched with a few wide scalar loads
         // before its pairs, instead of one load and wait per pair
@@ -373,18 +376,20 @@ __global__ void __launch_bounds__(kWave *WPB)
             // x_j / x_i = 2^(j-i) exactly on the doubling grid
             const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
             const float Sm = A + Bm;
-            {
-              float s = Ls.get(i), c = Lc.get(i);
-              comp_add_pos(s, c, A);
-              Ls.set(i, s);
-              Lc.set(i, c);
-            }
-            comp_add_pos(as, ac, A);
+            // every FP32 amount enters its FP64 sums exactly: the sums
+            // round only at FP64 precision, and gain and loss of a
+            // transfer carry the same value
+            const double Ad = (double)A;
+            L.set(i, L.get(i) + Ad);
+            as += Ad;
             if (has_flux) {
-              float lam = lmj1 - __builtin_amdgcn_logf(mjg + Sm);
+              int ed;
+              float fd;
+              log2_split(mjg + Sm, ed, fd);
+              float lam = (float)(ej1 - ed) + (fj1 - fd);
               lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
               const float F = flux_fraction_f32(cc[u], cc[u + 1], lam) * Sm;
-              comp_add_pos(fs, fc, F);
+              fs += (double)F;
             }
           }
         }
@@ -397,12 +402,11 @@ __global__ void __launch_bounds__(kWave *WPB)
         }
         // S5 bound: losses as the smaller partner + self pair + every flux
         // leaving bin j (>= the negative merged nets); FP32 margin.
-        const float demand = (Ls.get(j) + Lc.get(j)) + self2 + (fs + fc);
-        flag = flag || (mj > 0.0f && demand > mj * (1.0f - 1e-5f));
-        // the row's compensated sums meet in FP64: bin j keeps the mass
-        // arriving from smaller partners less what it passes on to j+1
-        const double out = ((double)fs + (double)fc) + (double)self2;
-        gj = ((double)as + (double)ac) - out;
+        const double out = fs + (double)self2;
+        flag = flag || (mj > 0.0f && L.get(j) + out > mj * (1.0 - 1e-5));
+        // bin j keeps the mass arriving from smaller partners less what it
+        // passes on to j+1
+        gj = as - out;
         if (j + 1 <= B - 1) g += out;
         step_pairs += row_pairs<B>(act, j);
       }

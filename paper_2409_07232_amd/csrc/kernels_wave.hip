@@ -57,13 +57,14 @@ struct AccF64 {
   __device__ __forceinline__ double val() const { return v; }
 };
 
+// FP32 amounts summed in FP64: each amount enters exactly, so the gain and
+// the loss side of a transfer carry the same value and the sums round only
+// at FP64 precision (an FP64 add issues at the rate of an FP32 one).
 struct AccF32 {
-  float s, c;
-  __device__ __forceinline__ void zero() { s = c = 0.0f; }
-  __device__ __forceinline__ void add(float x) { comp_add(s, c, x); }
-  __device__ __forceinline__ double val() const {
-    return (double)s + (double)c;
-  }
+  double v;
+  __device__ __forceinline__ void zero() { v = 0.0; }
+  __device__ __forceinline__ void add(float x) { v += (double)x; }
+  __device__ __forceinline__ double val() const { return v; }
 };
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
@@ -99,7 +100,7 @@ __device__ __forceinline__ void entry_amounts(float K, float tau,
 
 // Flux that a pair with merged mass Sm landing in bin qt moves on to qt+1;
 // the gain and the loss side call the same function with the same inputs.
-__device__ __forceinline__ double entry_flux(bool has_flux, const double *Mt,
+__device__ __noinline__ double entry_flux(bool has_flux, const double *Mt,
                                              const double *lnM, int qt,
                                              double c, double Sm) {
   if (!has_flux) return 0.0;
@@ -137,35 +138,44 @@ __device__ __forceinline__ T pair_scale(const T *sg, int qa, int qb, bool ta,
   return s;
 }
 
-// Per-bin accumulators of a pass in LDS: FP64 one array each, FP32 a
-// (sum, compensation) pair of arrays each.
-template <bool F32>
-struct PassLds;
-template <>
-struct PassLds<false> {
+// One batch of rows [r, r + NB) of a lane's stream (rows at or past
+// r1 read as padding).  on[u]: entry u is a pair of two active bins; its
+// operands are loaded only then (and the Courant number only if with_c).
+template <int NB, typename Real, typename Real2, typename RealC>
+__device__ __forceinline__ void batch_fetch(
+    const uint2 *__restrict__ idx, const Real2 *__restrict__ ke,
+    const Real2 *__restrict__ xe, const RealC *__restrict__ ce, bool with_c,
+    int r, int r1, int lane, const Real *mass, uint2 (&id)[NB],
+    bool (&on)[NB], Real2 (&kb)[NB], Real2 (&xb)[NB], RealC (&cb)[NB]) {
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    id[u] = r + u < r1 ? idx[(size_t)(r + u) * kWave + lane]
+                       : make_uint2(0u, 0u);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
+    on[u] = ((id[u].y >> 16) & kWValid) != 0 && mass[qa] != (Real)0 &&
+            mass[qb] != (Real)0;
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if (!on[u]) continue;
+    const size_t pos = (size_t)(r + u) * kWave + lane;
+    kb[u] = ke[pos];
+    xb[u] = xe[pos];
+    if (with_c) cb[u] = ce[pos];
+  }
+}
+
+// Per-bin accumulators of a pass in LDS, FP64 in both modes.
+struct PassLds {
   double *gain, *fout, *loss, *dneg;
   // a bin's entries of one species-pair block, added to its sum
-  __device__ void merge(double *arr, int q, const AccF64 &a) const {
-    arr[q] += a.v;
+  template <typename Acc>
+  __device__ void merge(double *arr, int q, const Acc &a) const {
+    arr[q] += a.val();
   }
   __device__ double read(const double *arr, int q) const { return arr[q]; }
-};
-template <>
-struct PassLds<true> {
-  float *gain, *fout, *loss, *dneg;  // each [2][SB]: sums then compensations
-  int SB;
-  __device__ void merge(float *arr, int q, const AccF32 &a) const {
-    AccF32 t;
-    t.s = arr[q];
-    t.c = arr[SB + q];
-    t.add(a.s);
-    t.c += a.c;
-    arr[q] = t.s;
-    arr[SB + q] = t.c;
-  }
-  __device__ double read(const float *arr, int q) const {
-    return (double)arr[q] + (double)arr[SB + q];
-  }
 };
 
 // One step of one point by one wave (S1-S6).  Returns 1 if the limiter ran;
@@ -189,28 +199,21 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   typedef typename std::conditional<F32, float2, double2>::type Real2;
   const int lane = threadIdx.x;
   const int B = m.B, S = m.S, SB = m.S * m.B;
-  // LDS (8 SB doubles): masses, numbers, log-masses, then the pass sums and
-  // the limiter factors
+  // LDS: masses, numbers and log-masses (3 SB Real, at offset 0 so that a
+  // bin's address is its index scaled), then the FP64 pass sums (4 SB
+  // doubles from the next 8-byte boundary), then the limiter factors (FP64
+  // mode, SB doubles) or the exponents of the split mass logs (FP32 mode,
+  // SB ints); wave_lds_bytes gives the total
   Real *mass = (Real *)lds;
   Real *nv = mass + SB;
   Real *lnm = nv + SB;
-  Real *acc0 = lnm + SB;
-  PassLds<F32> P;
-  if constexpr (F32) {
-    P.SB = SB;
-    P.gain = acc0;
-    P.fout = acc0 + 2 * SB;
-    P.loss = acc0 + 4 * SB;
-    P.dneg = acc0 + 6 * SB;
-  } else {
-    P.gain = acc0;
-    P.fout = acc0 + SB;
-    P.loss = acc0 + 2 * SB;
-    P.dneg = acc0 + 3 * SB;
-  }
-  double *sg = (double *)(lds + (size_t)7 * SB * sizeof(double));
-  // FP32 mode: exponents of the split mass logs, after the pass sums
-  int *lne = (int *)(acc0 + 8 * SB);
+  PassLds P;
+  P.gain = (double *)(lds + ((3 * SB * sizeof(Real) + 7) & ~(size_t)7));
+  P.fout = P.gain + SB;
+  P.loss = P.gain + 2 * SB;
+  P.dneg = P.gain + 3 * SB;
+  double *sg = P.gain + 4 * SB;
+  int *lne = (int *)(P.gain + 4 * SB);
 
   // S1/S2: owned bins, FP64 total, activity (a bin's mass is recomputed
   // from its state where needed rather than kept in registers)
@@ -244,14 +247,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     }
     // the pass sums of a bin with no entries stay zero (its owner writes
     // every other bin's sums in the passes)
-    if constexpr (F32) {
-      P.gain[q] = P.gain[SB + q] = 0.0f;
-      P.fout[q] = P.fout[SB + q] = 0.0f;
-      P.loss[q] = P.loss[SB + q] = 0.0f;
-      P.dneg[q] = P.dneg[SB + q] = 0.0f;
-    } else {
-      P.gain[q] = P.fout[q] = P.loss[q] = P.dneg[q] = 0.0;
-    }
+    P.gain[q] = P.fout[q] = P.loss[q] = P.dneg[q] = 0.0;
   }
   __syncthreads();
   // species present at this point: pairs of absent species are skipped
@@ -276,9 +272,23 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     ke = m.we_k64 + (size_t)br * nrows;
   }
 
+  typedef typename std::conditional<F32, float2, double>::type RealC;
+  const RealC *ce;
+  if constexpr (F32)
+    ce = m.we_c32;
+  else
+    ce = m.we_c64;
+
+  // rows per batch (FP64 operands take twice the registers)
+  constexpr int NB = F32 ? 4 : 2;
+
   bool lim = false;
   for (int pass = 0; pass < 2; ++pass) {
-    // S3/S4 gains over this lane's gain stream, species pair by pair
+    // S3/S4 gains over this lane's gain stream, species pair by pair.  The
+    // stream is walked NB rows at a time: the rows' entry words, then
+    // the masses of their bins, then the operands of the active entries
+    // are each fetched for the whole batch before any of them is used, so
+    // a batch waits for about two memory latencies instead of two per row.
     for (int sa = 0, ab = 0; sa < S; ++sa)
       for (int sb = sa; sb < S; ++sb, ++ab) {
         if (!((pres >> sa) & (pres >> sb) & 1ull)) continue;
@@ -288,64 +298,69 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         f.zero();
         d.zero();
         int cur = -1;
-#pragma unroll 2
-        for (int r = r0; r < r1; ++r) {
-          const size_t pos = (size_t)r * kWave + lane;
-          const uint2 id = m.we_idx[pos];
-          const unsigned fl = id.y >> 16;
-          if (!(fl & kWValid)) continue;  // padding at the block's end
-          const int qt = (int)(id.y & 0xffffu);
-          if (qt != cur) {
-            if (cur >= 0) {
-              P.merge(P.gain, cur, g);
-              P.merge(P.fout, cur, f);
-              if (pass == 0) P.merge(P.dneg, cur, d);
+        for (int r = r0; r < r1; r += NB) {
+          uint2 id[NB];
+          bool on[NB];
+          Real2 kb[NB], xb[NB];
+          RealC cb[NB];
+          batch_fetch<NB>(m.we_idx, ke, xe, ce, true, r, r1, lane, mass,
+                            id, on, kb, xb, cb);
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const unsigned fl = id[u].y >> 16;
+            if (!(fl & kWValid)) continue;  // padding at the block's end
+            const int qt = (int)(id[u].y & 0xffffu);
+            if (qt != cur) {
+              if (cur >= 0) {
+                P.merge(P.gain, cur, g);
+                P.merge(P.fout, cur, f);
+                if (pass == 0) P.merge(P.dneg, cur, d);
+              }
+              cur = qt;
+              g.zero();
+              f.zero();
+              d.zero();
             }
-            cur = qt;
-            g.zero();
-            f.zero();
-            d.zero();
-          }
-          const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
-          if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
-          const Real2 kk = ke[pos];
-          Real A, Bm;
-          entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb,
-                        (fl & kWSelf) != 0, xe[pos], A, Bm);
-          Real F;
-          if constexpr (F32)
-            F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt, m.we_c32[pos],
-                           A + Bm);
-          else
-            F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, m.we_c64[pos],
-                           A + Bm);
-          const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-          if (pass == 1) {
-            const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
-                                       Bm, F);
-            A *= sc;
-            Bm *= sc;
-            F *= sc;
-          }
-          if constexpr (F32) {
-            // exact transfers: the same rounded amounts as the source side
-            if (!ta) g.add(A);
-            if (!tb) g.add(Bm);
-            g.add(-F);
-          } else {
-            // the pair's combined contribution to its target in one
-            // rounding (a target that is also a source keeps the other
-            // source's mass)
-            const double keep = ta ? Bm : (tb ? A : A + Bm);
-            g.add(keep - F);
-          }
-          f.add(F);
-          if (pass == 0) {
-            if (ta || tb) {
-              const Real keep = ta ? Bm : A;
-              if (F > keep) d.add(F - keep);
+            if (!on[u]) continue;
+            const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
+            Real A, Bm;
+            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, nv, qa, qb,
+                          (fl & kWSelf) != 0, xb[u], A, Bm);
+            Real F;
+            if constexpr (F32)
+              F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt, cb[u],
+                             A + Bm);
+            else
+              F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, cb[u],
+                             A + Bm);
+            const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+            if (pass == 1) {
+              const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
+                                         Bm, F);
+              A *= sc;
+              Bm *= sc;
+              F *= sc;
             }
-            ++npairs;
+            if constexpr (F32) {
+              // exact transfers: the same rounded amounts as the source side
+              if (!ta) g.add(A);
+              if (!tb) g.add(Bm);
+              g.add(-F);
+            } else {
+              // the pair's combined contribution to its target in one
+              // rounding (a target that is also a source keeps the other
+              // source's mass)
+              const double keep = ta ? Bm : (tb ? A : A + Bm);
+              g.add(keep - F);
+            }
+            f.add(F);
+            if (pass == 0) {
+              if (ta || tb) {
+                const Real keep = ta ? Bm : A;
+                if (F > keep) d.add(F - keep);
+              }
+              ++npairs;
+            }
           }
         }
         if (cur >= 0) {
@@ -355,7 +370,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         }
       }
     // losses over this lane's loss stream: the same collided amounts, seen
-    // from the source bins
+    // from the source bins (the Courant numbers only matter in the second
+    // pass, where the pair's scale needs its flux)
     for (int sa = 0, ab = 0; sa < S; ++sa)
       for (int sb = sa; sb < S; ++sb, ++ab) {
         if (!((pres >> sa) & (pres >> sb) & 1ull)) continue;
@@ -363,49 +379,54 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         Acc lo;
         lo.zero();
         int cur = -1;
-#pragma unroll 2
-        for (int r = r0; r < r1; ++r) {
-          const size_t pos = (size_t)r * kWave + lane;
-          const uint2 id = m.we_idx[pos];
-          const unsigned fl = id.y >> 16;
-          if (!(fl & kWValid)) continue;
-          const int qa = (int)(id.x & 0xffffu), qb = (int)(id.x >> 16);
-          const bool sideb = (fl & kWSideB) != 0;
-          const int q = sideb ? qb : qa;
-          if (q != cur) {
-            if (cur >= 0) P.merge(P.loss, cur, lo);
-            cur = q;
-            lo.zero();
-          }
-          if (mass[qa] == (Real)0 || mass[qb] == (Real)0) continue;
-          const Real2 kk = ke[pos];
-          const bool self = (fl & kWSelf) != 0;
-          Real A, Bm;
-          entry_amounts(fma(kk.y, wr, kk.x), tdt, nv, qa, qb, self, xe[pos],
-                        A, Bm);
-          if (pass == 1) {
-            // the pair's scale, as its target's owner computes it
-            const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-            const int qt = (int)(id.y & 0xffffu);
-            Real F = (Real)0;
-            if (ta || tb) {
-              if constexpr (F32)
-                F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt,
-                               m.we_c32[pos], A + Bm);
-              else
-                F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt,
-                               m.we_c64[pos], A + Bm);
+        for (int r = r0; r < r1; r += NB) {
+          uint2 id[NB];
+          bool on[NB];
+          Real2 kb[NB], xb[NB];
+          RealC cb[NB];
+          batch_fetch<NB>(m.we_idx, ke, xe, ce, pass == 1, r, r1, lane,
+                            mass, id, on, kb, xb, cb);
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const unsigned fl = id[u].y >> 16;
+            if (!(fl & kWValid)) continue;
+            const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
+            const bool sideb = (fl & kWSideB) != 0;
+            const int q = sideb ? qb : qa;
+            if (q != cur) {
+              if (cur >= 0) P.merge(P.loss, cur, lo);
+              cur = q;
+              lo.zero();
             }
-            const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
-                                       Bm, F);
-            A *= sc;
-            Bm *= sc;
-          }
-          if (self) {
-            lo.add(A);
-            lo.add(Bm);
-          } else {
-            lo.add(sideb ? Bm : A);
+            if (!on[u]) continue;
+            const bool self = (fl & kWSelf) != 0;
+            Real A, Bm;
+            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, nv, qa, qb, self,
+                          xb[u], A, Bm);
+            if (pass == 1) {
+              // the pair's scale, as its target's owner computes it
+              const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+              const int qt = (int)(id[u].y & 0xffffu);
+              Real F = (Real)0;
+              if (ta || tb) {
+                if constexpr (F32)
+                  F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt,
+                                 cb[u], A + Bm);
+                else
+                  F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, cb[u],
+                                 A + Bm);
+              }
+              const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
+                                         Bm, F);
+              A *= sc;
+              Bm *= sc;
+            }
+            if (self) {
+              lo.add(A);
+              lo.add(Bm);
+            } else {
+              lo.add(sideb ? Bm : A);
+            }
           }
         }
         if (cur >= 0) P.merge(P.loss, cur, lo);
@@ -441,7 +462,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     for (int o = 0; o < kMaxOwn; ++o) {
       const int q = own[o];
       if (q < 0) continue;
-      P.gain[q] = P.fout[q] = P.loss[q] = (Real)0;
+      P.gain[q] = P.fout[q] = P.loss[q] = 0.0;
     }
     __syncthreads();  // sigma visible before the second pass
   }
@@ -451,20 +472,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
-    double gq;
-    if constexpr (F32) {
-      AccF32 ga;
-      ga.s = P.gain[q];
-      ga.c = P.gain[SB + q];
-      if (q % B != 0) {
-        ga.add(P.fout[q - 1]);
-        ga.add(P.fout[SB + q - 1]);
-      }
-      gq = ga.val();
-    } else {
-      gq = P.gain[q];
-      if (q % B != 0) gq += P.fout[q - 1];
-    }
+    double gq = P.gain[q];
+    if (q % B != 0) gq += P.fout[q - 1];
     double net = gq - P.read(P.loss, q);
     if constexpr (F32) net *= Mtot;
     const double xq = m.x[q % B];
@@ -476,47 +485,84 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   return lim ? 1u : 0u;
 }
 
-// Persistent over the compacted slots of every grid.  FP32C: a point whose
-// step needs the limiter is marked pending (steps of the call left) and
-// skipped from then on.  pending_only: FP64 steps for the marked points.
+// The steps of one slot: a launch's steps (FP32C: until a step needs the
+// limiter or drains a bin, then the slot is marked pending with the steps
+// of the call left), or the pending steps in FP64 mode.
+template <bool F32>
+__device__ __forceinline__ void slot_steps(const WaveArgs &a,
+                                           const WaveGrid &G,
+                                           const short *own, int slot,
+                                           int pend, unsigned char *lds,
+                                           unsigned long long &npairs,
+                                           unsigned long long &nlim,
+                                           unsigned long long &nfp64) {
+  const DevModel &m = G.m;
+  const int SB = m.S * m.B;
+  int br = 0;
+  for (int b = 1; b < m.nbr; ++b)
+    if (slot >= G.meta->bucket_base[b]) br = b;
+  const double w = G.wgt[slot];
+  double *st = G.state + (size_t)slot * SB;
+  const int n = a.pending_only ? pend : a.nsteps;
+  for (int step = 0; step < n; ++step) {
+    const unsigned r = point_step<F32>(m, own, st, w, br, a.dt, lds, npairs);
+    if (F32 && r == 2u) {
+      if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
+      break;
+    }
+    nlim += r;
+  }
+  if (a.pending_only) {
+    nfp64 += (unsigned long long)pend;
+    if (threadIdx.x == 0) G.pending[slot] = 0;
+  }
+}
+
+// Persistent waves over the compacted slots of every grid, handed out one
+// at a time from a counter (counters[3], zero at the start of the call): a
+// point's cost varies with its species and spectrum, and the FP64 steps of
+// pending points are few and of very different lengths, so waves take work
+// as they free up.  Every wave's loop ends on exactly one fetch past the
+// last slot, so launch k of a call starts its numbering at k (slots +
+// waves).  FP32C: a point whose step needs the limiter is marked pending
+// (steps of the call left) and skipped from then on; pending_only: FP64
+// steps for the marked points.
 template <bool F32>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(2))) wave_step(WaveArgs a) {
   extern __shared__ unsigned char lds[];
   unsigned long long npairs = 0, nlim = 0, nfp64 = 0;
-  for (int g = 0; g < a.ngrids; ++g) {
-    const WaveGrid &G = a.g[g];
-    const DevModel &m = G.m;
-    const int SB = m.S * m.B;
-    const int nslots = G.meta->nslots;
-    short own[kMaxOwn];
-#pragma unroll
-    for (int o = 0; o < kMaxOwn; ++o) own[o] = m.own[threadIdx.x * kMaxOwn + o];
-    for (int slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
-      const int pt = G.slot_point[slot];
-      if (pt < 0) continue;  // padding
-      const int pend = G.pending[slot];
-      if (a.pending_only ? pend <= 0 : pend != 0) continue;
-      int br = 0;
-      for (int b = 1; b < m.nbr; ++b)
-        if (slot >= G.meta->bucket_base[b]) br = b;
-      const double w = G.wgt[slot];
-      double *st = G.state + (size_t)slot * SB;
-      const int n = a.pending_only ? pend : a.nsteps;
-      for (int step = 0; step < n; ++step) {
-        const unsigned r =
-            point_step<F32>(m, own, st, w, br, a.dt, lds, npairs);
-        if (F32 && r == 2u) {
-          if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
-          break;
-        }
-        nlim += r;
-      }
-      if (a.pending_only) {
-        nfp64 += (unsigned long long)pend;
-        if (threadIdx.x == 0) G.pending[slot] = 0;
-      }
+  long long total = 0;
+  for (int g = 0; g < a.ngrids; ++g) total += a.g[g].meta->nslots;
+  const unsigned long long base =
+      (unsigned long long)a.launch_idx *
+      (unsigned long long)(total + (long long)gridDim.x);
+  int gown = -1;
+  short own[kMaxOwn];
+  for (;;) {
+    unsigned long long t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(&a.counters[3], 1ull);
+    // slot numbers of a launch stay below 2^31 (slots are int-indexed)
+    int rem = uniform((int)(__shfl(t, 0) - base));
+    int g = 0;
+    while (g < a.ngrids && rem >= a.g[g].meta->nslots) {
+      rem -= a.g[g].meta->nslots;
+      ++g;
     }
+    g = uniform(g);
+    if (g >= a.ngrids) break;
+    const WaveGrid &G = a.g[g];
+    const int slot = uniform(rem);
+    if (G.slot_point[slot] < 0) continue;  // padding
+    const int pv = uniform(G.pending[slot]);
+    if (a.pending_only ? pv <= 0 : pv != 0) continue;
+    if (g != gown) {
+#pragma unroll
+      for (int o = 0; o < kMaxOwn; ++o)
+        own[o] = G.m.own[threadIdx.x * kMaxOwn + o];
+      gown = g;
+    }
+    slot_steps<F32>(a, G, own, slot, pv, lds, npairs, nlim, nfp64);
   }
   npairs = wave_sum_u64(npairs);
   if (threadIdx.x == 0) {
@@ -533,10 +579,11 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
   int sb = 0;
   for (int g = 0; g < a.ngrids; ++g)
     sb = a.g[g].m.S * a.g[g].m.B > sb ? a.g[g].m.S * a.g[g].m.B : sb;
-  // FP64 steps: 8 doubles per bin; FP32C steps: 3 + 8 floats per bin (the
-  // limiter factors are only used by FP64 steps)
+  // LDS per wave (see point_step): 3 Real per bin, padded to 8 bytes, then
+  // 4 FP64 sums and a limiter factor (FP64) or an exponent (FP32C) per bin
   const bool f64 = precision == 0 || a.pending_only;
-  const size_t lds = (size_t)sb * (f64 ? 8 * sizeof(double) : 12 * sizeof(float));
+  const size_t lds = f64 ? (size_t)sb * 64
+                         : (((size_t)sb * 12 + 7) & ~(size_t)7) + (size_t)sb * 36;
   if (f64)
     hipLaunchKernelGGL(wave_step<false>, dim3(blocks), dim3(kWave), lds, st,
                        a);

@@ -59,7 +59,7 @@ def test_thunderstorm_patch_small(precision):
     got, st, _ = run_gpu(w, precision)
     dry = ~w.cloudy()
     assert np.array_equal(got[dry], w.N[dry])
-    check(got, ref, w.N, x, precision, "patch16", limited=lim)
+    check(got, ref, w.N, x, precision, "patch16", limited=lim, w=w)
     assert st["active_points"] == int((~dry).sum())
 
 
@@ -73,7 +73,8 @@ def test_ragged_point_counts(precision, npts):
     sub.nsteps = 20
     ref, x, lim = run_oracle(sub)
     got, _, _ = run_gpu(sub, precision)
-    check(got, ref, sub.N, x, precision, "ragged%d" % npts, limited=lim)
+    check(got, ref, sub.N, x, precision, "ragged%d" % npts, limited=lim,
+          w=sub)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -184,6 +185,7 @@ def test_full_size_thunderstorm_sampled(precision):
     assert np.all(got >= 0)
     sub = w.subset(idx)
     ref, x, lim = run_oracle(sub)
-    check(got, ref, sub.N, x, precision, "full-sampled", limited=lim)
+    check(got, ref, sub.N, x, precision, "full-sampled", limited=lim,
+          w=sub)
     st = h.stats()
     assert st["active_points"] == int(cl.sum())

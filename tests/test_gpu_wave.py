@@ -48,7 +48,7 @@ def test_wave_kernel_single_species(precision):
     w.nsteps = 40
     ref, x, lim = run_oracle(w)
     got, st, _ = gpu_run(w, precision, flags=L.FLAG_FORCE_WAVE)
-    check(got, ref, w.N, x, precision, "wave-patch", limited=lim)
+    check(got, ref, w.N, x, precision, "wave-patch", limited=lim, w=w)
     dry = ~w.cloudy()
     assert np.array_equal(got[dry], w.N[dry])
 
@@ -61,7 +61,7 @@ def test_four_species(precision):
     ref, x, lim = run_oracle(w)
     got, st, _ = gpu_run(w, precision)
     assert st["kernel"] == 1 and st["active_points"] == 300
-    check(got, ref, w.N, x, precision, "four-species", limited=lim)
+    check(got, ref, w.N, x, precision, "four-species", limited=lim, w=w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -72,7 +72,8 @@ def test_four_species_long(precision):
     ref, x, lim = run_oracle(w)
     got, st, _ = gpu_run(w, precision)
     assert st["limiter_steps"] > 0 and lim.sum() > 0
-    check(got, ref, w.N, x, precision, "four-species-100", limited=lim)
+    check(got, ref, w.N, x, precision, "four-species-100", limited=lim,
+          w=w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -82,7 +83,8 @@ def test_refined_grids(precision, nbins, npts, nsteps):
     w = wl.config4(nbins=nbins, npoints=npts, nsteps=nsteps)
     ref, x, lim = run_oracle(w)
     got, _, _ = gpu_run(w, precision)
-    check(got, ref, w.N, x, precision, "refined%d" % nbins, limited=lim)
+    check(got, ref, w.N, x, precision, "refined%d" % nbins, limited=lim,
+          w=w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -121,7 +123,7 @@ def test_multi_grid_launch(precision):
         assert np.array_equal(single, outs[0][g])
         ref, x, lim = run_oracle(w)
         check(outs[0][g], ref, w.N, x, precision, "multi-%s" % w.name,
-              limited=lim)
+              limited=lim, w=w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
