@@ -160,6 +160,9 @@ struct WaveTables {
   std::vector<short> own;
   int rows_g = 0, rows_l = 0;
   std::vector<int> blk;  // [npairs][4]: gain rows offset, count; loss same
+  std::vector<int> fixb; // [npairs][4]: gain fix-up offset, count; loss same
+  std::vector<uint2> fix;  // .x = bin | first lane << 16, .y = last lane |
+                           // (first lane's slot) << 16
   std::vector<uint2> idx;
   std::vector<float2> x32, c32, k32;
   std::vector<double2> x64, k64;
@@ -197,8 +200,9 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
             if (qb != qt) Lq[qb].push_back({a, i, b, j, true});
           }
         }
-  // longest-processing-time assignment of bins to lanes; a gain entry costs
-  // about four loss entries
+  // bins of the per-bin work (activity, limiter test, update): a
+  // longest-processing-time assignment by entry counts, at most kMaxOwn
+  // bins per lane
   std::vector<int> order(SB);
   std::vector<double> wgt(SB);
   for (int q = 0; q < SB; ++q) {
@@ -217,29 +221,57 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
     wt.own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
     load[best] += wgt[q];
   }
-  // per lane and species pair (a <= b): the entries of its bins, in owned
-  // bin order; a block of rows per species pair, padded to its longest lane
+  // Streams: per species pair (a <= b) and side, the entries of every bin
+  // in bin order, cut into kWave contiguous segments of equal length (one
+  // per lane, entry e of lane l at row e): every lane has work in every row
+  // but the last.  A bin whose entries span several lanes is shared: each
+  // of those lanes leaves its partial sum in a slot (0 for the first bin
+  // of its segment, 1 for the last) and a fix-up adds the partials in lane
+  // order after the block.
   const int npairs = S * (S + 1) / 2;
   auto pair_of = [&](const Pair &pr) {
     return pr.a * S - (pr.a * (pr.a - 1)) / 2 + (pr.b - pr.a);
   };
-  std::vector<std::vector<std::vector<Pair>>> gl(
-      kWave, std::vector<std::vector<Pair>>(npairs)),
-      ll(kWave, std::vector<std::vector<Pair>>(npairs));
-  for (int l = 0; l < kWave; ++l)
-    for (int o = 0; o < kMaxOwn; ++o) {
-      const int q = wt.own[(size_t)l * kMaxOwn + o];
-      if (q < 0) continue;
-      for (const Pair &pr : T[q]) gl[l][pair_of(pr)].push_back(pr);
-      for (const Pair &pr : Lq[q]) ll[l][pair_of(pr)].push_back(pr);
-    }
+  struct Ent {
+    Pair pr;
+    int q;
+  };
+  // seg[side][ab][lane]: the lane's entries; shared[side][ab]: bins
+  std::vector<std::vector<std::vector<std::vector<Ent>>>> seg(
+      2, std::vector<std::vector<std::vector<Ent>>>(
+             npairs, std::vector<std::vector<Ent>>(kWave)));
+  std::vector<std::vector<std::vector<char>>> shared(
+      2, std::vector<std::vector<char>>(npairs, std::vector<char>(SB, 0)));
   wt.blk.assign((size_t)npairs * 4, 0);
+  wt.fixb.assign((size_t)npairs * 4, 0);
   int rows = 0;
   for (int side = 0; side < 2; ++side)
     for (int ab = 0; ab < npairs; ++ab) {
-      int len = 0;
-      for (int l = 0; l < kWave; ++l)
-        len = std::max(len, (int)(side ? ll : gl)[l][ab].size());
+      std::vector<Ent> all;
+      for (int q = 0; q < SB; ++q)
+        for (const Pair &pr : (side ? Lq : T)[q])
+          if (pair_of(pr) == ab) all.push_back({pr, q});
+      const int n = (int)all.size();
+      const int len = (n + kWave - 1) / kWave;
+      for (int e = 0; e < n; ++e) seg[side][ab][e / len].push_back(all[e]);
+      // shared bins and their fix-up entries
+      wt.fixb[(size_t)ab * 4 + 2 * side] = (int)wt.fix.size();
+      for (int e = 0; e < n;) {
+        int f = e;
+        while (f < n && all[f].q == all[e].q) ++f;
+        const int l0 = e / len, l1 = (f - 1) / len;
+        if (l1 > l0) {
+          shared[side][ab][all[e].q] = 1;
+          // the first lane holds the bin in slot 0 only if its segment
+          // starts with this bin
+          const unsigned slot0 = (e % len == 0) ? 0u : 1u;
+          wt.fix.push_back(make_uint2((unsigned)all[e].q | ((unsigned)l0 << 16),
+                                      (unsigned)l1 | (slot0 << 16)));
+        }
+        e = f;
+      }
+      wt.fixb[(size_t)ab * 4 + 2 * side + 1] =
+          (int)wt.fix.size() - wt.fixb[(size_t)ab * 4 + 2 * side];
       wt.blk[(size_t)ab * 4 + 2 * side] = rows;
       wt.blk[(size_t)ab * 4 + 2 * side + 1] = len;
       rows += len;
@@ -254,11 +286,12 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
   wt.c64.assign(n, 0.0);
   wt.k32.assign(n * nbr, make_float2(0.f, 0.f));
   wt.k64.assign(n * nbr, make_double2(0.0, 0.0));
-  auto put = [&](size_t pos, const Pair &pr, bool loss_side) {
+  auto put = [&](size_t pos, const Pair &pr, bool loss_side, bool shr) {
     const int k = h->kt[(size_t)pr.i * B + pr.j];
     const int P = h->product[(size_t)pr.a * S + pr.b];
     const int qt = P * B + k, qa = pr.a * B + pr.i, qb = pr.b * B + pr.j;
     unsigned fl = kWValid;
+    if (shr) fl |= kWShared;
     if (qa == qt) fl |= kWTA;
     if (qb == qt) fl |= kWTB;
     if (qa == qb) fl |= kWSelf;
@@ -279,15 +312,15 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
       wt.k64[(size_t)br * n + pos] = make_double2(Kd[t], Kd[t + 1]);
     }
   };
-  for (int l = 0; l < kWave; ++l)
-    for (int ab = 0; ab < npairs; ++ab) {
-      for (size_t e = 0; e < gl[l][ab].size(); ++e)
-        put((size_t)(wt.blk[(size_t)ab * 4] + e) * kWave + l, gl[l][ab][e],
-            false);
-      for (size_t e = 0; e < ll[l][ab].size(); ++e)
-        put((size_t)(wt.blk[(size_t)ab * 4 + 2] + e) * kWave + l,
-            ll[l][ab][e], true);
-    }
+  for (int side = 0; side < 2; ++side)
+    for (int ab = 0; ab < npairs; ++ab)
+      for (int l = 0; l < kWave; ++l) {
+        const auto &sg = seg[side][ab][l];
+        for (size_t e = 0; e < sg.size(); ++e)
+          put((size_t)(wt.blk[(size_t)ab * 4 + 2 * side] + e) * kWave + l,
+              sg[e].pr, side == 1, shared[side][ab][sg[e].q] != 0);
+      }
+  if (wt.fix.empty()) wt.fix.push_back(make_uint2(0u, 0u));
   return FSBM_OK;
 }
 
@@ -400,6 +433,8 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       {wt.k32.data(), sizeof(float2) * wt.k32.size(), 0},
       {wt.k64.data(), sizeof(double2) * wt.k64.size(), 0},
       {wt.blk.data(), sizeof(int) * wt.blk.size(), 0},
+      {wt.fixb.data(), sizeof(int) * wt.fixb.size(), 0},
+      {wt.fix.data(), sizeof(uint2) * wt.fix.size(), 0},
   };
   size_t off = 0;
   for (auto &p : parts) {
@@ -447,6 +482,8 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.we_k32 = (const float2 *)at(21);
   m.we_k64 = (const double2 *)at(22);
   m.wblk = (const int *)at(23);
+  m.wfixb = (const int *)at(24);
+  m.wfix = (const uint2 *)at(25);
   return FSBM_OK;
 }
 

@@ -46,16 +46,21 @@ struct DevModel {
   const float *KfT;
   const double *ctT;
   const float *ctfT;  // [j][i][2]: FP32 Courant number c and c * kLn2f
-  // one-point-per-wave kernel: bins owned by each lane ([64][kMaxOwn], -1
-  // padded) and, per lane, a stream of gain entries (the pairs landing in
-  // its bins) and a stream of loss entries (the pairs its bins lose mass
-  // to), each entry holding the pair's static data.  Streams are
-  // interleaved by lane (entry r of lane l at r * 64 + l) and cut into one
-  // block of rows per species pair (a <= b), padded to the block's longest
-  // lane: gain blocks first (wrows_g rows), then loss blocks (wrows_l).
+  // one-point-per-wave kernel: bins of each lane's per-bin work ([64]
+  // [kMaxOwn], -1 padded) and two streams of pair entries, gain entries
+  // (grouped by the bin the pair lands in) and loss entries (grouped by the
+  // bin that loses mass), each entry holding the pair's static data.  Per
+  // species pair (a <= b) and side, the entries in bin order are cut into
+  // 64 contiguous equal segments, one per lane, interleaved by lane (entry
+  // r of lane l at r * 64 + l); gain blocks first (wrows_g rows), then loss
+  // blocks (wrows_l).  A bin whose entries span several lanes is shared
+  // (kWShared) and is summed by a fix-up after its block (wfix).
   const short *own;
   int wrows_g, wrows_l;
   const int *wblk;        // [npairs][4]: gain block row, rows; loss same
+  const int *wfixb;       // [npairs][4]: gain fix-up offset, count; loss
+  const uint2 *wfix;      // .x = bin | first lane << 16; .y = last lane |
+                          // slot of the bin in the first lane << 16
   const uint2 *we_idx;    // .x = qa | qb << 16, .y = q_target | flags << 16
   const float2 *we_x32;   // (x_i, x_j) FP32
   const double2 *we_x64;  // (x_i, x_j)
@@ -73,6 +78,7 @@ constexpr unsigned kWTB = 4u;     // qb is the target bin
 constexpr unsigned kWSelf = 8u;   // qa == qb (same species and bin)
 constexpr unsigned kWSideB = 16u; // loss entry: the owner is qb (else qa)
 constexpr unsigned kWFlux = 32u;  // the target is not the top bin: flux
+constexpr unsigned kWShared = 64u; // the entry's bin spans several lanes
 
 // Compaction results, written on the device (graph-capturable: no host
 // round trip).  Slots of one pressure bracket are contiguous and padded to a

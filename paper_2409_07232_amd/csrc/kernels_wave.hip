@@ -167,6 +167,16 @@ __device__ __forceinline__ void batch_fetch(
   }
 }
 
+// Byte offset of the shared-bin partial sums in a wave's LDS (after the
+// per-bin arrays, 8-byte aligned), and the wave's LDS size.
+template <bool F32>
+__host__ __device__ constexpr size_t wave_part_offset(int SB) {
+  return F32 ? ((((size_t)SB * 12 + 7) & ~(size_t)7) + (size_t)SB * 36 + 7) &
+                   ~(size_t)7
+             : (size_t)SB * 64;
+}
+constexpr size_t kWavePartBytes = 4 * 2 * kWave * sizeof(double);
+
 // Per-bin accumulators of a pass in LDS, FP64 in both modes.
 struct PassLds {
   double *gain, *fout, *loss, *dneg;
@@ -214,6 +224,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   P.dneg = P.gain + 3 * SB;
   double *sg = P.gain + 4 * SB;
   int *lne = (int *)(P.gain + 4 * SB);
+  // partial sums of shared bins: [4 accumulators][2 slots][64 lanes], from
+  // the next 8-byte boundary after the per-bin arrays (wave_lds_bytes)
+  double *psum = (double *)(lds + wave_part_offset<F32>(SB));
 
   // S1/S2: owned bins, FP64 total, activity (a bin's mass is recomputed
   // from its state where needed rather than kept in registers)
@@ -298,6 +311,23 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         f.zero();
         d.zero();
         int cur = -1;
+        bool cur_shared = false, first_flush = true;
+        // a bin's sums go to LDS directly, or (shared bin) to this lane's
+        // slot: 0 for the first bin of its segment, 1 for the last
+        auto flush = [&]() {
+          if (cur < 0) return;
+          if (cur_shared) {
+            const int sl = first_flush ? 0 : 1;
+            psum[(0 * 2 + sl) * kWave + lane] = g.val();
+            psum[(1 * 2 + sl) * kWave + lane] = f.val();
+            psum[(2 * 2 + sl) * kWave + lane] = d.val();
+          } else {
+            P.merge(P.gain, cur, g);
+            P.merge(P.fout, cur, f);
+            if (pass == 0) P.merge(P.dneg, cur, d);
+          }
+          first_flush = false;
+        };
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
@@ -311,12 +341,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             if (!(fl & kWValid)) continue;  // padding at the block's end
             const int qt = (int)(id[u].y & 0xffffu);
             if (qt != cur) {
-              if (cur >= 0) {
-                P.merge(P.gain, cur, g);
-                P.merge(P.fout, cur, f);
-                if (pass == 0) P.merge(P.dneg, cur, d);
-              }
+              flush();
               cur = qt;
+              cur_shared = (fl & kWShared) != 0;
               g.zero();
               f.zero();
               d.zero();
@@ -363,10 +390,28 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             }
           }
         }
-        if (cur >= 0) {
-          P.merge(P.gain, cur, g);
-          P.merge(P.fout, cur, f);
-          if (pass == 0) P.merge(P.dneg, cur, d);
+        flush();
+        // fix-up: each shared bin's partials summed in lane order
+        const int fo = m.wfixb[ab * 4], fn = m.wfixb[ab * 4 + 1];
+        if (fn > 0) {
+          __syncthreads();
+          for (int t = lane; t < fn; t += kWave) {
+            const uint2 fx = m.wfix[fo + t];
+            const int q = (int)(fx.x & 0xffffu), l0 = (int)(fx.x >> 16);
+            const int l1 = (int)(fx.y & 0xffffu), s0 = (int)(fx.y >> 16);
+            double sg0 = psum[(0 * 2 + s0) * kWave + l0];
+            double sf0 = psum[(1 * 2 + s0) * kWave + l0];
+            double sd0 = psum[(2 * 2 + s0) * kWave + l0];
+            for (int l = l0 + 1; l <= l1; ++l) {
+              sg0 += psum[(0 * 2) * kWave + l];
+              sf0 += psum[(1 * 2) * kWave + l];
+              sd0 += psum[(2 * 2) * kWave + l];
+            }
+            P.gain[q] += sg0;
+            P.fout[q] += sf0;
+            if (pass == 0) P.dneg[q] += sd0;
+          }
+          __syncthreads();
         }
       }
     // losses over this lane's loss stream: the same collided amounts, seen
@@ -379,6 +424,15 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         Acc lo;
         lo.zero();
         int cur = -1;
+        bool cur_shared = false, first_flush = true;
+        auto flush = [&]() {
+          if (cur < 0) return;
+          if (cur_shared)
+            psum[(3 * 2 + (first_flush ? 0 : 1)) * kWave + lane] = lo.val();
+          else
+            P.merge(P.loss, cur, lo);
+          first_flush = false;
+        };
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
@@ -394,8 +448,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             const bool sideb = (fl & kWSideB) != 0;
             const int q = sideb ? qb : qa;
             if (q != cur) {
-              if (cur >= 0) P.merge(P.loss, cur, lo);
+              flush();
               cur = q;
+              cur_shared = (fl & kWShared) != 0;
               lo.zero();
             }
             if (!on[u]) continue;
@@ -429,7 +484,20 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             }
           }
         }
-        if (cur >= 0) P.merge(P.loss, cur, lo);
+        flush();
+        const int fo = m.wfixb[ab * 4 + 2], fn = m.wfixb[ab * 4 + 3];
+        if (fn > 0) {
+          __syncthreads();
+          for (int t = lane; t < fn; t += kWave) {
+            const uint2 fx = m.wfix[fo + t];
+            const int q = (int)(fx.x & 0xffffu), l0 = (int)(fx.x >> 16);
+            const int l1 = (int)(fx.y & 0xffffu), s0 = (int)(fx.y >> 16);
+            double sl = psum[(3 * 2 + s0) * kWave + l0];
+            for (int l = l0 + 1; l <= l1; ++l) sl += psum[(3 * 2) * kWave + l];
+            P.loss[q] += sl;
+          }
+          __syncthreads();
+        }
       }
     // every pass sum and outgoing flux visible to all lanes
     __syncthreads();
@@ -579,11 +647,13 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
   int sb = 0;
   for (int g = 0; g < a.ngrids; ++g)
     sb = a.g[g].m.S * a.g[g].m.B > sb ? a.g[g].m.S * a.g[g].m.B : sb;
-  // LDS per wave (see point_step): 3 Real per bin, padded to 8 bytes, then
-  // 4 FP64 sums and a limiter factor (FP64) or an exponent (FP32C) per bin
+  // LDS per wave (see point_step): 3 Real per bin, padded to 8 bytes, 4
+  // FP64 sums and a limiter factor (FP64) or an exponent (FP32C) per bin,
+  // then the partial sums of shared bins
   const bool f64 = precision == 0 || a.pending_only;
-  const size_t lds = f64 ? (size_t)sb * 64
-                         : (((size_t)sb * 12 + 7) & ~(size_t)7) + (size_t)sb * 36;
+  const size_t lds = (f64 ? wave_part_offset<false>(sb)
+                          : wave_part_offset<true>(sb)) +
+                     kWavePartBytes;
   if (f64)
     hipLaunchKernelGGL(wave_step<false>, dim3(blocks), dim3(kWave), lds, st,
                        a);
