@@ -61,3 +61,43 @@ def test_no_cpu_fallback_in_binding():
             _lib.load("/nonexistent/libfsbm_coal.so")
         finally:
             _lib._lib = saved
+
+
+def _create(nbins, nspecies, opts):
+    import numpy as np
+    lib = _lib.load()
+    npairs = nspecies * (nspecies + 1) // 2
+    tables = np.full(npairs * nbins * nbins, 1e-4)
+    plev = np.array([1000.0])
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    prod = (ctypes.c_int32 * (nspecies * nspecies))()
+    if nspecies > 1:
+        opts.product = ctypes.cast(prod, ctypes.POINTER(ctypes.c_int32))
+    return lib.fsbm_coal_create(nbins, nspecies, tables.ctypes.data_as(dp), 1,
+                                plev.ctypes.data_as(dp), ctypes.byref(opts),
+                                ctypes.byref(h))
+
+
+def test_sequential_order_shapes_rejected_without_device_work():
+    """The sequential form exists for one species on the doubling grid in
+    FP64 with the lane kernel's bin counts; everything else is refused at
+    create time, before any device call."""
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.fsbm_coal_opts_default(ctypes.byref(o))
+    assert o.order == _lib.ORDER_SIMULTANEOUS
+    o.order = _lib.ORDER_SEQUENTIAL
+    o.precision = _lib.FSBM_FP32C
+    assert _create(33, 1, o) == _lib.FSBM_EUNSUPPORTED
+    o.precision = _lib.FSBM_FP64
+    assert _create(33, 2, o) == _lib.FSBM_EUNSUPPORTED
+    assert _create(66, 1, o) == _lib.FSBM_EUNSUPPORTED      # not a lane size
+    o.s = 2
+    assert _create(33, 1, o) == _lib.FSBM_EUNSUPPORTED      # refined grid
+    o.s = 1
+    o.flags = _lib.FLAG_FORCE_WAVE
+    assert _create(33, 1, o) == _lib.FSBM_EUNSUPPORTED
+    o.flags = 0
+    o.order = 7
+    assert _create(33, 1, o) == _lib.FSBM_EINVAL
