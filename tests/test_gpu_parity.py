@@ -189,3 +189,25 @@ def test_full_size_thunderstorm_sampled(precision):
           w=sub)
     st = h.stats()
     assert st["active_points"] == int(cl.sum())
+
+
+def _varied_golovin(nbins, npts=70, nsteps=40, seed=5):
+    """Golovin runs on a B-bin doubling grid, points varied by a seeded
+    overall scale and per-bin noise (ragged count: one full wave + 6)."""
+    w = wl.config1(npoints=npts, nbins=nbins, nsteps=nsteps, dt=2.0)
+    rng = np.random.default_rng(seed)
+    scale = np.exp(rng.uniform(-1.0, 1.0, (npts, 1, 1)))
+    noise = rng.uniform(0.8, 1.2, w.N.shape)
+    w.N = np.ascontiguousarray(w.N * scale * noise)
+    return w
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nbins", [3, 8, 16, 40])
+def test_every_lane_bin_count(precision, nbins):
+    """Each bin count the one-point-per-lane kernels are built for."""
+    w = _varied_golovin(nbins)
+    ref, x, lim = run_oracle(w)
+    got, st, _ = run_gpu(w, precision)
+    assert st["kernel"] == 0
+    check(got, ref, w.N, x, precision, "lane%d" % nbins, limited=lim, w=w)

@@ -205,3 +205,37 @@ def test_full_size_thunderstorm_sampled():
     sub = w.subset(idx)
     ref, x, lim = run_oracle(sub, order=1)
     check(got, ref, sub.N, x, 0, "seq-full-sampled", limited=lim)
+
+
+@pytest.mark.parametrize("nbins", [3, 8, 16, 40])
+def test_every_bin_count(nbins):
+    """Each bin count the sequential kernel is built for (Golovin runs,
+    points varied by a seeded scale and per-bin noise, 70 points)."""
+    w = wl.config1(npoints=70, nbins=nbins, nsteps=40, dt=2.0)
+    rng = np.random.default_rng(5)
+    w.N = np.ascontiguousarray(w.N * np.exp(rng.uniform(-1, 1, (70, 1, 1))) *
+                               rng.uniform(0.8, 1.2, w.N.shape))
+    ref, x, lim = run_oracle(w, order=1)
+    got, st, _ = run_gpu(w)
+    assert st["kernel"] == 2
+    check(got, ref, w.N, x, 0, "seq%d" % nbins, limited=lim)
+
+
+def test_degenerate_calls():
+    L = _lib()
+    w = wl.config2(nx=8, ny=8, nz=50)
+    h = seq_handle(w)
+    got, _, _ = run_gpu(w, nsteps=0, handle=h)
+    assert np.array_equal(got, w.N)
+    dry = np.zeros_like(w.N)
+    got, st, _ = run_gpu(w, N=dry, handle=h)
+    assert np.array_equal(got, dry)
+    assert st["active_points"] == 0
+    Nd = torch.zeros((0, 1, w.nbins), dtype=torch.float64, device="cuda")
+    pd = torch.zeros((0,), dtype=torch.float64, device="cuda")
+    h.step(Nd, pd, 2.0, 5)
+    with pytest.raises(L.FsbmError) as e:
+        Nd = torch.from_numpy(w.N.copy()).to("cuda")
+        pd = torch.from_numpy(w.p.copy()).to("cuda")
+        h.step(Nd, pd, -1.0, 5)
+    assert e.value.code == L.FSBM_EINVAL
