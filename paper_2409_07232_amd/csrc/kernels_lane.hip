@@ -346,9 +346,20 @@ __global__ void __launch_bounds__(kWave *WPB)
         const bool has_flux = j <= B - 2;
         // slope logs split into exact exponents and mantissa logs (see
         // log2_split: the tail's masses are tiny and their logs large)
-        int ej1 = 0;
-        float fj1 = 0.0f;
-        if (has_flux) log2_split(m.get(j + 1), ej1, fj1);
+        // lam = log2 m_{j+1} - log2(m_j + Sm)
+        //     = [log2 m_{j+1} - log2 m_j] - log2(1 + Sm / m_j):
+        // the bracket once per row from split logs, the rest per pair as
+        // the log of a value in [1, 2) for most pairs
+        float lrow = 0.0f, imj = 0.0f;
+        if (has_flux) {
+          int e1, e0;
+          float f1, f0;
+          log2_split(m.get(j + 1), e1, f1);
+          log2_split(mjg, e0, f0);
+          lrow = (float)(e1 - e0) + (f1 - f0);
+          imj = __builtin_amdgcn_rcpf(mjg);
+          imj = __builtin_fmaf(imj, __builtin_fmaf(-mjg, imj, 1.0f), imj);
+        }
         const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
         const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, c ln 2)
         double as = 0.0;  // mass arriving in bin j
@@ -383,10 +394,8 @@ __global__ void __launch_bounds__(kWave *WPB)
             L.set(i, L.get(i) + Ad);
             as += Ad;
             if (has_flux) {
-              int ed;
-              float fd;
-              log2_split(mjg + Sm, ed, fd);
-              float lam = (float)(ej1 - ed) + (fj1 - fd);
+              float lam =
+                  lrow - __builtin_amdgcn_logf(1.0f + Sm * imj);
               lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
               const float F = flux_fraction_f32(cc[u], cc[u + 1], lam) * Sm;
               fs += (double)F;
