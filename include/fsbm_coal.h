@@ -104,7 +104,10 @@ void fsbm_coal_opts_default(fsbm_coal_opts *opts);
  *  opts           NULL for defaults
  *  out            receives the handle
  * Errors: FSBM_EINVAL (sizes, levels, product map, non-finite or negative
- * table entries), FSBM_ENOMEM, FSBM_EHIP.  Uses the current HIP device.
+ * table entries), FSBM_EUNSUPPORTED (B > 512, more than 8 pressure brackets,
+ * or S*B > 768 where the one-point-per-lane kernels do not apply; checked
+ * before any device call), FSBM_ENOMEM, FSBM_EHIP.  Uses the current HIP
+ * device.
  */
 int fsbm_coal_create(int32_t nbins, int32_t nspecies,
                      const double *kernel_tables, int32_t nlevels,

@@ -836,6 +836,12 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
       (!lane_kernel_supported(nbins, nspecies, o.s) ||
        o.precision != FSBM_FP64 || (o.flags & FSBM_FLAG_FORCE_WAVE)))
     return FSBM_EUNSUPPORTED;
+  // shapes no kernel takes: the one-point-per-wave kernel holds at most
+  // kMaxOwn bins per lane
+  if ((!lane_kernel_supported(nbins, nspecies, o.s) ||
+       (o.flags & FSBM_FLAG_FORCE_WAVE)) &&
+      nspecies * nbins > kWave * kMaxOwn)
+    return FSBM_EUNSUPPORTED;
   for (int l = 0; l < nlevels; ++l)
     if (!isfinite(p_levels_hpa[l])) return FSBM_EINVAL;
   for (int l = 0; l + 1 < nlevels; ++l)

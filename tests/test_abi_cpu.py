@@ -101,3 +101,18 @@ def test_sequential_order_shapes_rejected_without_device_work():
     o.flags = 0
     o.order = 7
     assert _create(33, 1, o) == _lib.FSBM_EINVAL
+
+
+def test_shapes_beyond_the_kernels_rejected_without_device_work():
+    """S x B above 64 lanes x 12 bins (the one-point-per-wave kernel's
+    largest shape), more than 512 bins or more than 8 species are refused
+    at create time, before any device call."""
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.fsbm_coal_opts_default(ctypes.byref(o))
+    o.s = 12
+    assert _create(400, 2, o) == _lib.FSBM_EUNSUPPORTED
+    o.s = 1
+    assert _create(97, 8, o) == _lib.FSBM_EUNSUPPORTED
+    assert _create(513, 1, o) == _lib.FSBM_EUNSUPPORTED
+    assert _create(33, 9, o) == _lib.FSBM_EINVAL

@@ -140,3 +140,57 @@ def test_autotune_keeps_results(precision, tmp_path, monkeypatch):
         assert np.array_equal(before, after)
         assert st["steps_per_launch"] >= 1
     assert (tmp_path / "tune.txt").exists()
+
+
+def _custom(nbins, s, nspecies, npts, nsteps, seed):
+    """nspecies species on a grid of s bins per mass doubling: gravitational
+    kernels with a distinct fall-speed exponent per species (so all
+    S (S + 1) / 2 pair tables differ), product map max(a, b), seeded
+    gamma spectra with per-species mean radii in random active windows
+    (as in the benchmark workloads: the tail bins of most points limit)."""
+    rng = np.random.default_rng(seed)
+    rho = tuple([1.0] * nspecies)
+    beta = tuple(0.3 + 0.5 * a / max(nspecies - 1, 1)
+                 for a in range(nspecies))
+    rbar = tuple(10e-4 * (1.0 + a) for a in range(nspecies))
+    tables = wl.gravitational_tables(nbins, s, rho, beta,
+                                     wl.multi_species_vcoef(beta),
+                                     wl.P_LEVELS_3)
+    prod = np.maximum.outer(np.arange(nspecies),
+                            np.arange(nspecies)).astype(np.int32)
+    x = wl.bin_masses(nbins, s)
+    N = wl._multi_species_states(
+        rng, x, rho, rbar, tuple([(0.05, 0.5)] * nspecies),
+        np.ones((npts, nspecies), dtype=bool), npts,
+        ((0, 5 * s), (15 * s, min(24 * s, nbins - 1))))
+    p = rng.uniform(500.0, 1000.0, npts)
+    return wl.Workload("custom", nbins, nspecies, s, tables,
+                       wl.P_LEVELS_3.copy(), prod, N, p, 2.0, nsteps)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_grid(precision):
+    """S x B = 768, the largest one-point-per-wave shape: 2 species x 384
+    bins (mass ratio 2^(1/12)), a full wave of lanes with 12 bins each."""
+    w = _custom(384, 12, 2, 3, 2, seed=21)
+    ref, x, lim = run_oracle(w)
+    got, st, _ = gpu_run(w, precision)
+    assert st["kernel"] == 1
+    check(got, ref, w.N, x, precision, "grid768", limited=lim, w=w)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eight_species(precision):
+    """The largest species count: 8 species x 33 bins, 36 pair tables."""
+    w = _custom(33, 1, 8, 70, 10, seed=22)
+    ref, x, lim = run_oracle(w)
+    got, st, _ = gpu_run(w, precision)
+    check(got, ref, w.N, x, precision, "species8", limited=lim, w=w)
+
+
+def test_beyond_the_largest_shape_is_refused():
+    L = _lib()
+    w = _custom(400, 12, 2, 1, 1, seed=23)
+    with pytest.raises(L.FsbmError) as e:
+        L.FsbmCoal.from_workload(w, precision=L.FSBM_FP64)
+    assert e.value.code == L.FSBM_EUNSUPPORTED
