@@ -151,10 +151,34 @@ __device__ __forceinline__ float flux_fraction_f32(float c, float cl2,
   return __builtin_fminf(c * e * g, 1.0f);
 }
 
+// The same fraction from the half slope h = lam / 2 and ys = 2 c ln 2, so
+// that y = ys h and 2^(lam/2) = 2^h need no multiply by 1/2.  Every value
+// equals the one flux_fraction_f32 forms from lam = 2h (scaling by 2 is
+// exact): y, the Taylor branch, and the exponent -c lam = -(c h + c h).
+__device__ __forceinline__ float flux_fraction_half_f32(float c, float ys,
+                                                        float h) {
+  const float y = ys * h;
+  const float e = __builtin_amdgcn_exp2f(h);
+  float g;
+  if (__builtin_fabsf(y) < 0.25f) {
+    g = 1.0f + y * (-0.5f + y * (1.0f / 6.0f + y * (-1.0f / 24.0f +
+                                                    y * (1.0f / 120.0f -
+                                                         y * (1.0f / 720.0f)))));
+  } else {
+    float r = __builtin_amdgcn_rcpf(y);
+    r = __builtin_fmaf(r, __builtin_fmaf(-y, r, 1.0f), r);
+    const float u = c * h;
+    g = (1.0f - __builtin_amdgcn_exp2f(-(u + u))) * r;
+  }
+  return __builtin_fminf(c * e * g, 1.0f);
+}
+
 // x1 bounds in base-2 units: the empty-neighbour floor, and a ceiling at
 // x1 = 173 where f(c, x1) >= 1 already holds for every c >= 3e-38 (so the
 // clamp of f decides) while 2^(lam/2) stays finite.
 constexpr float kLamFloor = (float)(kX1Floor / 0.69314718055994530942);
 constexpr float kLamCeil = (float)(173.0 / 0.69314718055994530942);
+constexpr float kHalfLamFloor = 0.5f * kLamFloor;
+constexpr float kHalfLamCeil = 0.5f * kLamCeil;
 
 }  // namespace fsbm

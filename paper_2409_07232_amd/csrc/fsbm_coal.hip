@@ -393,11 +393,12 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   for (int i = 0; i < B; ++i)
     for (int j = 0; j < B; ++j) {
       ctT[(size_t)j * B + i] = h->ct[(size_t)i * B + j];
-      // FP32 Courant number and its product with ln 2, rounded as the
-      // kernels would round it
+      // FP32 Courant number and twice its product with ln 2 (the product
+      // rounded as the one-point-per-wave kernel rounds it; doubling is
+      // exact)
       const float cf = ctf[(size_t)i * B + j];
       ctfT[((size_t)j * B + i) * 2] = cf;
-      ctfT[((size_t)j * B + i) * 2 + 1] = cf * kLn2f;
+      ctfT[((size_t)j * B + i) * 2 + 1] = 2.0f * (cf * kLn2f);
     }
   WaveTables wt;
   const bool wave_ok = S * B <= kWave * kMaxOwn;

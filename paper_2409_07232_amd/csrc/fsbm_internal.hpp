@@ -45,7 +45,7 @@ struct DevModel {
   const double *KdT;
   const float *KfT;
   const double *ctT;
-  const float *ctfT;  // [j][i][2]: FP32 Courant number c and c * kLn2f
+  const float *ctfT;  // [j][i][2]: FP32 Courant number c and 2 (c * kLn2f)
   // one-point-per-wave kernel: bins of each lane's per-bin work ([64]
   // [kMaxOwn], -1 padded) and two streams of pair entries, gain entries
   // (grouped by the bin the pair lands in) and loss entries (grouped by the

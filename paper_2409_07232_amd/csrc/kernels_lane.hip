@@ -350,18 +350,19 @@ __global__ void __launch_bounds__(kWave *WPB)
         //     = [log2 m_{j+1} - log2 m_j] - log2(1 + Sm / m_j):
         // the bracket once per row from split logs, the rest per pair as
         // the log of a value in [1, 2) for most pairs
-        float lrow = 0.0f, imj = 0.0f;
+        // (carried as halves: h = lam / 2 = hrow - log2(1 + Sm / m_j) / 2)
+        float hrow = 0.0f, imj = 0.0f;
         if (has_flux) {
           int e1, e0;
           float f1, f0;
           log2_split(m.get(j + 1), e1, f1);
           log2_split(mjg, e0, f0);
-          lrow = (float)(e1 - e0) + (f1 - f0);
+          hrow = 0.5f * ((float)(e1 - e0) + (f1 - f0));
           imj = __builtin_amdgcn_rcpf(mjg);
           imj = __builtin_fmaf(imj, __builtin_fmaf(-mjg, imj, 1.0f), imj);
         }
         const float *Kj = Kf + (size_t)j * B * 2;  // row j: [i][2]
-        const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, c ln 2)
+        const float *cj = ctf + (size_t)j * B * 2;  // row j: [i](c, 2c ln 2)
         double as = 0.0;  // mass arriving in bin j
         // columns in chunks of 8: the chunk's table entries (kernel pair and
         // Courant pair per column) are fetched with a few wide scalar loads
@@ -384,9 +385,10 @@ __global__ void __launch_bounds__(kWave *WPB)
             const int u = 2 * (i - i0);
             const float tK = __builtin_fmaf(kk[u + 1], tjw, tj * kk[u]);
             const float A = tK * m.get(i);
-            // x_j / x_i = 2^(j-i) exactly on the doubling grid
-            const float Bm = __builtin_amdgcn_ldexpf(A, j - i);
-            const float Sm = A + Bm;
+            // x_j / x_i = 2^(j-i) exactly on the doubling grid: the merged
+            // mass A + A 2^(j-i), rounded once
+            const float p2 = __builtin_bit_cast(float, (127 + j - i) << 23);
+            const float Sm = __builtin_fmaf(A, p2, A);
             // every FP32 amount enters its FP64 sums exactly: the sums
             // round only at FP64 precision, and gain and loss of a
             // transfer carry the same value
@@ -394,10 +396,12 @@ __global__ void __launch_bounds__(kWave *WPB)
             L.set(i, L.get(i) + Ad);
             as += Ad;
             if (has_flux) {
-              float lam =
-                  lrow - __builtin_amdgcn_logf(1.0f + Sm * imj);
-              lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
-              const float F = flux_fraction_f32(cc[u], cc[u + 1], lam) * Sm;
+              float h = __builtin_fmaf(
+                  __builtin_amdgcn_logf(__builtin_fmaf(Sm, imj, 1.0f)), -0.5f,
+                  hrow);
+              h = __builtin_amdgcn_fmed3f(h, kHalfLamFloor, kHalfLamCeil);
+              const float F =
+                  flux_fraction_half_f32(cc[u], cc[u + 1], h) * Sm;
               fs += (double)F;
             }
           }
