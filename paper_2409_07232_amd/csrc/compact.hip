@@ -6,11 +6,14 @@
 // Here a point is cloudy iff it holds mass; collisions neither create nor
 // remove a point's mass, so the cloudy set is fixed for the whole call and
 // is built once per call:
-//   count   per block of points: cloudy points per pressure bracket
+//   count   per block of points: a cloudy flag per point (the block's rows
+//           read with coalesced loads) and cloudy points per pressure
+//           bracket
 //   scan    one block: exclusive scan over blocks, per bracket; bracket
 //           bases padded to whole waves so that each wave of the step
 //           kernels sees a single bracket
-//   gather  cloudy point -> slot (stable: point order within a bracket),
+//   gather  cloudy point (by its flag) -> slot (stable: point order within
+//           a bracket),
 //           bins copied into the structure-of-arrays workspace,
 //           interpolation weight and FP64 totals recorded
 //   sort    (one-point-per-lane kernels only) within chunks of 2048 slots,
@@ -47,30 +50,47 @@ __device__ __forceinline__ void bracket_of(const double *plev, int L,
   w = (p - plev[b + 1]) / (plev[b] - plev[b + 1]);
 }
 
-__device__ __forceinline__ bool point_is_cloudy(const double *row, int SB) {
-  bool any = false;
-  for (int q = 0; q < SB; ++q) any = any || (row[q] > 0.0);
-  return any;
-}
-
+// Cloudy flags and per-bracket counts of one block of points.  The block's
+// rows are one contiguous run of S*B doubles per point: its threads read
+// the run with consecutive addresses (one wave load covers 512 bytes) and
+// mark the point of every positive entry in LDS; the point of entry e is
+// e / SB, taken as the high word of e * magic with magic = ceil(2^32 / SB),
+// exact for every e < 256 SB.  Then each thread counts its own point.
 __global__ void __launch_bounds__(kCompactThreads)
     compact_count(const double *__restrict__ N, const double *__restrict__ p,
-                  int64_t npoints, int SB, const double *__restrict__ plev,
-                  int L, int *__restrict__ block_counts) {
+                  int64_t npoints, int SB, unsigned magic,
+                  const double *__restrict__ plev, int L,
+                  int *__restrict__ block_counts,
+                  unsigned char *__restrict__ cloudy) {
   __shared__ int cnt[kMaxBuckets];
-  if (threadIdx.x < kMaxBuckets) cnt[threadIdx.x] = 0;
+  __shared__ unsigned char wet[kCompactThreads];
+  const int t = threadIdx.x;
+  if (t < kMaxBuckets) cnt[t] = 0;
+  wet[t] = 0;
   __syncthreads();
-  const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
-  if (pt < npoints && point_is_cloudy(N + pt * SB, SB)) {
-    int l;
-    double w;
-    bracket_of(plev, L, p[pt], l, w);
-    atomicAdd(&cnt[l], 1);
+  // the grid covers the workspace's capacity: blocks past this call's
+  // points have no rows (np = 0) and count zero
+  const int64_t p0 = (int64_t)blockIdx.x * kCompactThreads;
+  const int np =
+      (int)max((int64_t)0, min((int64_t)kCompactThreads, npoints - p0));
+  const double *__restrict__ run = N + p0 * SB;
+  const unsigned total = (unsigned)np * (unsigned)SB;
+  for (unsigned e = t; e < total; e += kCompactThreads)
+    if (run[e] > 0.0) wet[__umulhi(e, magic)] = 1;
+  __syncthreads();
+  if (t < np) {
+    const bool c = wet[t] != 0;
+    cloudy[p0 + t] = c ? 1 : 0;
+    if (c) {
+      int l;
+      double w;
+      bracket_of(plev, L, p[p0 + t], l, w);
+      atomicAdd(&cnt[l], 1);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < kMaxBuckets)
-    block_counts[(size_t)blockIdx.x * kMaxBuckets + threadIdx.x] =
-        cnt[threadIdx.x];
+  if (t < kMaxBuckets)
+    block_counts[(size_t)blockIdx.x * kMaxBuckets + t] = cnt[t];
 }
 
 // One block of 1024 threads: exclusive scan of block counts per bracket.
@@ -129,7 +149,8 @@ __global__ void __launch_bounds__(kCompactThreads)
                    int *__restrict__ slot_point, double *__restrict__ state,
                    double *__restrict__ wgt, int slot_cap,
                    const double *__restrict__ x, double *__restrict__ tot,
-                   int aos, unsigned *__restrict__ keys, double theta) {
+                   int aos, unsigned *__restrict__ keys, double theta,
+                   const unsigned char *__restrict__ cloudy_flag) {
   constexpr int kWaves = kCompactThreads / kWave;
   __shared__ int wave_cnt[kWaves][kMaxBuckets];
   const int SB = S * B;
@@ -138,7 +159,7 @@ __global__ void __launch_bounds__(kCompactThreads)
   const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
   const bool inside = pt < npoints;
   const double *row = N + (inside ? pt : 0) * SB;
-  const bool cloudy = inside && point_is_cloudy(row, SB);
+  const bool cloudy = inside && cloudy_flag[pt] != 0;
   int l = 0;
   double w = 0.0;
   if (cloudy) bracket_of(plev, L, p[pt], l, w);
@@ -318,10 +339,16 @@ __global__ void check_state(const double *__restrict__ N, int64_t n,
 
 hipError_t launch_compact_count(const double *N, const double *p,
                                 int64_t npoints, int SB, const double *plev,
-                                int L, int *block_counts, int nblocks,
+                                int L, int *block_counts,
+                                unsigned char *cloudy, int nblocks,
                                 hipStream_t st) {
+  if (SB < 1 || SB > kWave * kMaxOwn ||
+      npoints > (int64_t)nblocks * kCompactThreads)
+    return hipErrorInvalidValue;
+  const unsigned magic = 0xffffffffu / (unsigned)SB + 1u;
   hipLaunchKernelGGL(compact_count, dim3(nblocks), dim3(kCompactThreads), 0,
-                     st, N, p, npoints, SB, plev, L, block_counts);
+                     st, N, p, npoints, SB, magic, plev, L, block_counts,
+                     cloudy);
   return hipGetLastError();
 }
 
@@ -341,11 +368,12 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  int *slot_point, double *state, double *wgt,
                                  int slot_cap, const double *x, double *tot,
                                  int aos, unsigned *keys, double theta,
+                                 const unsigned char *cloudy,
                                  hipStream_t st) {
   hipLaunchKernelGGL(compact_gather, dim3(nblocks), dim3(kCompactThreads), 0,
                      st, N, p, npoints, S, B, plev, L, block_offsets, meta,
                      slot_point, state, wgt, slot_cap, x, tot, aos, keys,
-                     theta);
+                     theta, cloudy);
   return hipGetLastError();
 }
 

@@ -526,6 +526,7 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   const size_t o_cnt = take(sizeof(unsigned long long) * 4);
   const size_t o_pend = take(sizeof(int) * cap);
   const size_t o_keys = h->lane ? take(sizeof(unsigned) * cap) : 0;
+  const size_t o_wet = take((size_t)npoints);
   drop_graph(h);
   if (h->wmem) hipFree(h->wmem);
   h->wmem = nullptr;
@@ -550,6 +551,7 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   h->ws.counters = (unsigned long long *)(b + o_cnt);
   h->ws.pending = (int *)(b + o_pend);
   h->ws.keys = h->lane ? (unsigned *)(b + o_keys) : nullptr;
+  h->ws.cloudy = b + o_wet;
   // pending[] is kept at zero by the kernels after this first clear
   e = hipMemset(h->ws.pending, 0, sizeof(int) * cap);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemset");
@@ -617,7 +619,7 @@ int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
   DevWork &w = h->ws;
   HIP_TRY(h, launch_zero_u64(w.counters, 4, st));
   HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
-                                  w.block_counts, h->nblocks, st));
+                                  w.block_counts, w.cloudy, h->nblocks, st));
   HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, h->nblocks,
                                  m.nbr, w.meta, st));
   // one point per lane: slots are ordered by top active bin and mass
@@ -627,7 +629,7 @@ int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
                                    w.block_offsets, w.meta, h->nblocks,
                                    w.slot_point, w.state, w.wgt, w.slot_cap,
                                    m.x, w.tot, aos ? 1 : 0, keys, m.theta,
-                                   st));
+                                   w.cloudy, st));
   HIP_TRY(h, launch_fill_padding(w.meta, w.slot_point, keys, w.slot_cap, st));
   if (keys)
     HIP_TRY(h, launch_compact_sort_load(N, w.meta, keys, w.slot_point, w.wgt,

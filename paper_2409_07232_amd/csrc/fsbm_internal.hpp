@@ -118,6 +118,7 @@ struct DevWork {
   unsigned *keys;        // [slot_cap] sort keys (lane kernels) or null
   int *pending;          // [slot_cap] steps of the call left for the exact
                          // FP64 path (0 = point still on the fast path)
+  unsigned char *cloudy;  // [npoints] 1 iff the point holds mass
   unsigned long long *counters;  // [4]: pair evals, limiter, fallback,
                                  // work-queue position of the wave kernel
 };
@@ -164,7 +165,8 @@ struct StepArgs {
 // --- host-side launchers (defined in the kernel translation units) -------
 hipError_t launch_compact_count(const double *N, const double *p,
                                 int64_t npoints, int SB, const double *plev,
-                                int L, int *block_counts, int nblocks,
+                                int L, int *block_counts,
+                                unsigned char *cloudy, int nblocks,
                                 hipStream_t st);
 hipError_t launch_compact_scan(const int *block_counts, int *block_offsets,
                                int nblocks, int nbuckets, CompactMeta *meta,
@@ -178,6 +180,7 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  double *wgt, int slot_cap,
                                  const double *x, double *tot, int aos,
                                  unsigned *keys, double theta,
+                                 const unsigned char *cloudy,
                                  hipStream_t st);
 hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
                                unsigned *keys, int slot_cap, hipStream_t st);

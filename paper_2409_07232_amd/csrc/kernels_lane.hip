@@ -452,24 +452,28 @@ __global__ void __launch_bounds__(kWave *WPB)
   add_counters(a.counters, npairs);
 }
 
-// Exact FP64 steps for lanes the fast kernels handed over.
+// Exact FP64 steps for lanes the fast kernels handed over.  The compacted
+// slot count is known on the device only, so a bounded grid strides over
+// the slots (usually none is pending).
 __global__ void __launch_bounds__(64) slow_steps(StepArgs a) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= a.meta->nslots) return;
-  const int n = a.pending[slot];
-  if (n <= 0) return;
-  int br = 0;
-  for (int b = 1; b < a.m.nbr; ++b)
-    if ((slot & ~(kWave - 1)) >= a.meta->bucket_base[b]) br = b;
-  unsigned long long pairs = 0, lim = 0;
-  for (int k = 0; k < n; ++k)
-    lim += slow_step_f64<kLaneMaxBins>(
-        a.m, a.state + state_index(0, slot, a.m.S * a.m.B), kWave,
-        a.wgt[slot], br, a.dt, &pairs);
-  a.pending[slot] = 0;
-  atomicAdd(&a.counters[0], pairs);
-  if (lim) atomicAdd(&a.counters[1], lim);
-  atomicAdd(&a.counters[2], (unsigned long long)n);
+  const int nslots = a.meta->nslots;
+  for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < nslots;
+       slot += gridDim.x * blockDim.x) {
+    const int n = a.pending[slot];
+    if (n <= 0) continue;
+    int br = 0;
+    for (int b = 1; b < a.m.nbr; ++b)
+      if ((slot & ~(kWave - 1)) >= a.meta->bucket_base[b]) br = b;
+    unsigned long long pairs = 0, lim = 0;
+    for (int k = 0; k < n; ++k)
+      lim += slow_step_f64<kLaneMaxBins>(
+          a.m, a.state + state_index(0, slot, a.m.S * a.m.B), kWave,
+          a.wgt[slot], br, a.dt, &pairs);
+    a.pending[slot] = 0;
+    atomicAdd(&a.counters[0], pairs);
+    if (lim) atomicAdd(&a.counters[1], lim);
+    atomicAdd(&a.counters[2], (unsigned long long)n);
+  }
 }
 
 template <int B, int WPB>
@@ -500,7 +504,7 @@ hipError_t launch_b(const StepArgs &a, int precision, int wpb, int max_slots,
 
 hipError_t launch_slow_steps(const StepArgs &a, int max_slots,
                              hipStream_t st) {
-  const int blocks = (max_slots + 63) / 64;
+  const int blocks = min((max_slots + 63) / 64, 2048);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(slow_steps, dim3(blocks), dim3(64), 0, st, a);
   return hipGetLastError();

@@ -211,3 +211,30 @@ def test_every_lane_bin_count(precision, nbins):
     got, st, _ = run_gpu(w, precision)
     assert st["kernel"] == 0
     check(got, ref, w.N, x, precision, "lane%d" % nbins, limited=lim, w=w)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["lane", "wave"])
+def test_handle_reused_on_fewer_points(precision, kind):
+    """A handle's workspace is sized by the largest call so far; a later
+    call on fewer points (compaction blocks past its last point, a ragged
+    tail inside a block) must equal a fresh handle's result bit for bit
+    and the oracle to the bar."""
+    L = _lib()
+    if kind == "lane":
+        w = wl.config2(nx=8, ny=8, nz=50)
+    else:
+        w = wl.config3(npoints=3000)
+    w.nsteps = 10
+    h = L.FsbmCoal.from_workload(w, precision=precision)
+    run_gpu(w, precision, handle=h)
+    idx = np.sort(np.random.default_rng(3).choice(w.npoints, 301,
+                                                  replace=False))
+    sub = w.subset(idx)
+    got, st, _ = run_gpu(sub, precision, handle=h)
+    fresh, _, _ = run_gpu(sub, precision)
+    assert np.array_equal(got, fresh)
+    assert st["kernel"] == (0 if kind == "lane" else 1)
+    ref, x, lim = run_oracle(sub)
+    check(got, ref, sub.N, x, precision, "reuse-" + kind, limited=lim,
+          w=sub)
