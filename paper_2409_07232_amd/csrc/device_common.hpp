@@ -125,36 +125,17 @@ __device__ __forceinline__ double flux_fraction_f64(double c, double x1) {
   return fmin(fmax(f, 0.0), 1.0);
 }
 
-// FP32 form on the base-2 log-slope lam = x1 / ln 2:
-//   f = c 2^(lam/2) g(y),  y = c x1,  g(y) = (1 - e^-y) / y,
+// FP32 form on the half base-2 log-slope h = x1 / (2 ln 2):
+//   f = c 2^h g(y),  y = c x1 = ys h with ys = 2 c ln 2,  g(y) = (1 - e^-y) / y,
 // with g from its Taylor series for |y| < 1/4 (truncation error below
-// 5e-8) and from the hardware exp2 otherwise.  cl2 = c ln 2.
+// 5e-8) and from the hardware exp2 otherwise, where e^-y = 2^-(2 c h) and
+// 2 c h = c h + c h exactly.  Carrying the half slope saves the multiply
+// by 1/2 in front of the exp2.
 // Errors here must be unbiased, not only small: the tail of a spectrum is
 // built over many steps from fluxes of this form, so a one-sided error of
 // 1e-7 in f adds up (measured: up to 2e-4 in bins holding 1e-9 of a
 // point's mass).  The hardware reciprocal of a negative y rounds toward
 // zero; one Newton step leaves a round-to-nearest error instead.
-__device__ __forceinline__ float flux_fraction_f32(float c, float cl2,
-                                                   float lam) {
-  const float y = cl2 * lam;
-  const float e = __builtin_amdgcn_exp2f(0.5f * lam);
-  float g;
-  if (__builtin_fabsf(y) < 0.25f) {
-    g = 1.0f + y * (-0.5f + y * (1.0f / 6.0f + y * (-1.0f / 24.0f +
-                                                    y * (1.0f / 120.0f -
-                                                         y * (1.0f / 720.0f)))));
-  } else {
-    float r = __builtin_amdgcn_rcpf(y);
-    r = __builtin_fmaf(r, __builtin_fmaf(-y, r, 1.0f), r);
-    g = (1.0f - __builtin_amdgcn_exp2f(-c * lam)) * r;
-  }
-  return __builtin_fminf(c * e * g, 1.0f);
-}
-
-// The same fraction from the half slope h = lam / 2 and ys = 2 c ln 2, so
-// that y = ys h and 2^(lam/2) = 2^h need no multiply by 1/2.  Every value
-// equals the one flux_fraction_f32 forms from lam = 2h (scaling by 2 is
-// exact): y, the Taylor branch, and the exponent -c lam = -(c h + c h).
 __device__ __forceinline__ float flux_fraction_half_f32(float c, float ys,
                                                         float h) {
   const float y = ys * h;
@@ -173,12 +154,10 @@ __device__ __forceinline__ float flux_fraction_half_f32(float c, float ys,
   return __builtin_fminf(c * e * g, 1.0f);
 }
 
-// x1 bounds in base-2 units: the empty-neighbour floor, and a ceiling at
-// x1 = 173 where f(c, x1) >= 1 already holds for every c >= 3e-38 (so the
-// clamp of f decides) while 2^(lam/2) stays finite.
-constexpr float kLamFloor = (float)(kX1Floor / 0.69314718055994530942);
-constexpr float kLamCeil = (float)(173.0 / 0.69314718055994530942);
-constexpr float kHalfLamFloor = 0.5f * kLamFloor;
-constexpr float kHalfLamCeil = 0.5f * kLamCeil;
+// Half-slope bounds (base 2): the empty-neighbour floor x1 = kX1Floor, and
+// a ceiling at x1 = 173 where f(c, x1) >= 1 already holds for every
+// c >= 3e-38 (so the clamp of f decides) while 2^h stays finite.
+constexpr float kHalfLamFloor = (float)(0.5 * kX1Floor / 0.69314718055994530942);
+constexpr float kHalfLamCeil = (float)(0.5 * 173.0 / 0.69314718055994530942);
 
 }  // namespace fsbm

@@ -302,8 +302,9 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
     wt.x32[pos] = make_float2(xf[pr.i], xf[pr.j]);
     wt.x64[pos] = make_double2(h->x[pr.i], h->x[pr.j]);
     const size_t ij = (size_t)pr.i * B + pr.j;
-    // FP32 Courant number and its product with ln 2 as the kernels round it
-    wt.c32[pos] = make_float2(ctf[ij], ctf[ij] * kLn2f);
+    // FP32 Courant number and twice its product with ln 2 (the product
+    // rounded in FP32, as the transposed lane table rounds it)
+    wt.c32[pos] = make_float2(ctf[ij], 2.0f * (ctf[ij] * kLn2f));
     wt.c64[pos] = h->ct[ij];
     const int ab = pair_of(pr);
     for (int br = 0; br < nbr; ++br) {
@@ -394,8 +395,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
     for (int j = 0; j < B; ++j) {
       ctT[(size_t)j * B + i] = h->ct[(size_t)i * B + j];
       // FP32 Courant number and twice its product with ln 2 (the product
-      // rounded as the one-point-per-wave kernel rounds it; doubling is
-      // exact)
+      // rounded in FP32; doubling is exact)
       const float cf = ctf[(size_t)i * B + j];
       ctfT[((size_t)j * B + i) * 2] = cf;
       ctfT[((size_t)j * B + i) * 2 + 1] = 2.0f * (cf * kLn2f);

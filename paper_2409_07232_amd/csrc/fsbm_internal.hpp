@@ -64,7 +64,7 @@ struct DevModel {
   const uint2 *we_idx;    // .x = qa | qb << 16, .y = q_target | flags << 16
   const float2 *we_x32;   // (x_i, x_j) FP32
   const double2 *we_x64;  // (x_i, x_j)
-  const float2 *we_c32;   // (c, c ln 2) FP32
+  const float2 *we_c32;   // (c, 2 c ln 2) FP32
   const double *we_c64;   // c
   const float2 *we_k32;   // [nbr][rows * 64] (K_{l+1}, K_l - K_{l+1}) FP32
   const double2 *we_k64;  // same, FP64

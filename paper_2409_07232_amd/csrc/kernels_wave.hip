@@ -75,12 +75,12 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
-// Collided amounts of one stream entry: A leaves qa, Bm leaves qb.
-__device__ __forceinline__ void entry_amounts(double K, double dt,
-                                              const double *Nv, int qa,
-                                              int qb, bool self, double2 x,
+// Collided amounts of one stream entry from the numbers na of bin qa and nb
+// of bin qb: A leaves qa, Bm leaves qb.
+__device__ __forceinline__ void entry_amounts(double K, double dt, double na,
+                                              double nb, bool self, double2 x,
                                               double &A, double &Bm) {
-  double C = dt * K * Nv[qa] * Nv[qb];
+  double C = dt * K * na * nb;
   if (self) C *= 0.5;
   A = C * x.x;
   Bm = C * x.y;
@@ -88,11 +88,10 @@ __device__ __forceinline__ void entry_amounts(double K, double dt,
 
 // The same in FP32 on numbers normalised by the point's mass (tau = dt
 // M_tot): amounts come out normalised by M_tot.
-__device__ __forceinline__ void entry_amounts(float K, float tau,
-                                              const float *n, int qa, int qb,
-                                              bool self, float2 x, float &A,
-                                              float &Bm) {
-  float C = ((tau * K) * n[qa]) * n[qb];
+__device__ __forceinline__ void entry_amounts(float K, float tau, float na,
+                                              float nb, bool self, float2 x,
+                                              float &A, float &Bm) {
+  float C = ((tau * K) * na) * nb;
   if (self) C *= 0.5f;
   A = C * x.x;
   Bm = C * x.y;
@@ -109,19 +108,17 @@ __device__ __noinline__ double entry_flux(bool has_flux, const double *Mt,
   return flux_fraction_f64(c, x1) * Sm;
 }
 
-// FP32: the base-2 log-slope from split logs (exponents exact), lm the
-// mantissa logs and le the exponents of the bin masses.
-__device__ __forceinline__ float entry_flux(bool has_flux, const float *m,
-                                            const float *lm, const int *le,
-                                            int qt, float2 c, float Sm) {
-  if (!has_flux) return 0.0f;
-  const float den = __builtin_fmaxf(m[qt] + Sm, 0x1p-120f);
-  int ed;
-  float fd;
-  log2_split(den, ed, fd);
-  float lam = (float)(le[qt + 1] - ed) + (lm[qt + 1] - fd);
-  lam = __builtin_amdgcn_fmed3f(lam, kLamFloor, kLamCeil);
-  return flux_fraction_f32(c.x, c.y, lam) * Sm;
+// FP32 flux of a gain entry: the target run's half slope bracket
+// hrow = (log2 m_{k+1} - log2 m_k) / 2 and guarded reciprocal im = 1 / m_k
+// come from the start of the run (see the gain loop); per entry only
+// log2(1 + Sm / m_k) remains, so that h = hrow - log2(1 + Sm / m_k) / 2 is
+// half the base-2 slope log2(m_{k+1} / (m_k + Sm)).  c = (c, 2 c ln 2).
+__device__ __forceinline__ float entry_flux_f32(float hrow, float im,
+                                                float2 c, float Sm) {
+  float h = __builtin_fmaf(
+      __builtin_amdgcn_logf(__builtin_fmaf(Sm, im, 1.0f)), -0.5f, hrow);
+  h = __builtin_amdgcn_fmed3f(h, kHalfLamFloor, kHalfLamCeil);
+  return flux_fraction_half_f32(c.x, c.y, h) * Sm;
 }
 
 // Limiter scale of a pair: the smallest sigma over the bins where the pair's
@@ -139,14 +136,17 @@ __device__ __forceinline__ T pair_scale(const T *sg, int qa, int qb, bool ta,
 }
 
 // One batch of rows [r, r + NB) of a lane's stream (rows at or past
-// r1 read as padding).  on[u]: entry u is a pair of two active bins; its
-// operands are loaded only then (and the Courant number only if with_c).
+// r1 read as padding).  na, nb: the numbers of the entry's two bins (zero
+// exactly for inactive bins); on[u]: entry u is a pair of two active bins;
+// its operands are loaded only then (and the Courant number only if
+// with_c).
 template <int NB, typename Real, typename Real2, typename RealC>
 __device__ __forceinline__ void batch_fetch(
     const uint2 *__restrict__ idx, const Real2 *__restrict__ ke,
     const Real2 *__restrict__ xe, const RealC *__restrict__ ce, bool with_c,
-    int r, int r1, int lane, const Real *mass, uint2 (&id)[NB],
-    bool (&on)[NB], Real2 (&kb)[NB], Real2 (&xb)[NB], RealC (&cb)[NB]) {
+    int r, int r1, int lane, const Real *num, uint2 (&id)[NB],
+    bool (&on)[NB], Real (&na)[NB], Real (&nb)[NB], Real2 (&kb)[NB],
+    Real2 (&xb)[NB], RealC (&cb)[NB]) {
 #pragma unroll
   for (int u = 0; u < NB; ++u)
     id[u] = r + u < r1 ? idx[(size_t)(r + u) * kWave + lane]
@@ -154,8 +154,10 @@ __device__ __forceinline__ void batch_fetch(
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
-    on[u] = ((id[u].y >> 16) & kWValid) != 0 && mass[qa] != (Real)0 &&
-            mass[qb] != (Real)0;
+    na[u] = num[qa];
+    nb[u] = num[qb];
+    on[u] = ((id[u].y >> 16) & kWValid) != 0 && na[u] != (Real)0 &&
+            nb[u] != (Real)0;
   }
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
@@ -312,6 +314,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         d.zero();
         int cur = -1;
         bool cur_shared = false, first_flush = true;
+        // FP32C: the current target's half slope bracket and 1 / m_k
+        float hrow = 0.0f, imq = 0.0f;
         // a bin's sums go to LDS directly, or (shared bin) to this lane's
         // slot: 0 for the first bin of its segment, 1 for the last
         auto flush = [&]() {
@@ -331,10 +335,11 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
+          Real na[NB], nb[NB];
           Real2 kb[NB], xb[NB];
           RealC cb[NB];
-          batch_fetch<NB>(m.we_idx, ke, xe, ce, true, r, r1, lane, mass,
-                            id, on, kb, xb, cb);
+          batch_fetch<NB>(m.we_idx, ke, xe, ce, true, r, r1, lane, nv, id,
+                          on, na, nb, kb, xb, cb);
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
             const unsigned fl = id[u].y >> 16;
@@ -347,26 +352,42 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
               g.zero();
               f.zero();
               d.zero();
+              if constexpr (F32) {
+                // the flux flag is the target's (not its species' top bin),
+                // so it holds for the whole run; an empty target is guarded
+                // as the one-point-per-lane kernel guards it
+                if (fl & kWFlux) {
+                  const float mg = mass[qt] + 0x1p-126f;
+                  int e0;
+                  float f0;
+                  log2_split(mg, e0, f0);
+                  hrow = 0.5f * ((float)(lne[qt + 1] - e0) + (lnm[qt + 1] - f0));
+                  const float r0 = __builtin_amdgcn_rcpf(mg);
+                  imq = __builtin_fmaf(r0, __builtin_fmaf(-mg, r0, 1.0f), r0);
+                }
+              }
             }
             if (!on[u]) continue;
             const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
             Real A, Bm;
-            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, nv, qa, qb,
+            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, na[u], nb[u],
                           (fl & kWSelf) != 0, xb[u], A, Bm);
             Real F;
             if constexpr (F32)
-              F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt, cb[u],
-                             A + Bm);
+              F = (fl & kWFlux) ? entry_flux_f32(hrow, imq, cb[u], A + Bm)
+                                : 0.0f;
             else
               F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, cb[u],
                              A + Bm);
             const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-            if (pass == 1) {
-              const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
-                                         Bm, F);
-              A *= sc;
-              Bm *= sc;
-              F *= sc;
+            if constexpr (!F32) {  // second pass: FP64 mode only
+              if (pass == 1) {
+                const double sc =
+                    pair_scale((const double *)sg, qa, qb, ta, tb, A, Bm, F);
+                A *= sc;
+                Bm *= sc;
+                F *= sc;
+              }
             }
             if constexpr (F32) {
               // exact transfers: the same rounded amounts as the source side
@@ -436,10 +457,11 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
+          Real na[NB], nb[NB];
           Real2 kb[NB], xb[NB];
           RealC cb[NB];
-          batch_fetch<NB>(m.we_idx, ke, xe, ce, pass == 1, r, r1, lane,
-                            mass, id, on, kb, xb, cb);
+          batch_fetch<NB>(m.we_idx, ke, xe, ce, pass == 1, r, r1, lane, nv,
+                          id, on, na, nb, kb, xb, cb);
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
             const unsigned fl = id[u].y >> 16;
@@ -456,25 +478,24 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             if (!on[u]) continue;
             const bool self = (fl & kWSelf) != 0;
             Real A, Bm;
-            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, nv, qa, qb, self,
-                          xb[u], A, Bm);
-            if (pass == 1) {
-              // the pair's scale, as its target's owner computes it
-              const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
-              const int qt = (int)(id[u].y & 0xffffu);
-              Real F = (Real)0;
-              if (ta || tb) {
-                if constexpr (F32)
-                  F = entry_flux((fl & kWFlux) != 0, mass, lnm, lne, qt,
-                                 cb[u], A + Bm);
-                else
+            entry_amounts(fma(kb[u].y, wr, kb[u].x), tdt, na[u], nb[u],
+                          self, xb[u], A, Bm);
+            // the second pass runs in FP64 mode only: an FP32C step that
+            // needs the limiter leaves the point to FP64 mode
+            if constexpr (!F32) {
+              if (pass == 1) {
+                // the pair's scale, as its target's owner computes it
+                const bool ta = (fl & kWTA) != 0, tb = (fl & kWTB) != 0;
+                const int qt = (int)(id[u].y & 0xffffu);
+                double F = 0.0;
+                if (ta || tb)
                   F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, cb[u],
                                  A + Bm);
+                const double sc =
+                    pair_scale((const double *)sg, qa, qb, ta, tb, A, Bm, F);
+                A *= sc;
+                Bm *= sc;
               }
-              const Real sc = pair_scale((const Real *)sg, qa, qb, ta, tb, A,
-                                         Bm, F);
-              A *= sc;
-              Bm *= sc;
             }
             if (self) {
               lo.add(A);
