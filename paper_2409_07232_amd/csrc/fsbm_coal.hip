@@ -456,6 +456,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.s = h->s;
   m.nbr = nbr;
   m.npairs = npairs;
+  m.bmagic = 0xffffffffu / (unsigned)B + 1u;
   m.theta = h->theta;
   m.x = (const double *)at(0);
   m.invx = (const double *)at(1);

@@ -28,6 +28,7 @@ struct DevModel {
   int B, S, L, s;
   int nbr;        // pressure brackets = max(L - 1, 1)
   int npairs;     // S (S + 1) / 2 species pairs
+  unsigned bmagic;  // ceil(2^32 / B): q / B = umulhi(q, bmagic) for q < 2^32 / B
   double theta;
   const double *x;      // [B] bin masses (g)
   const float *xf;      // [B] bin masses rounded to FP32

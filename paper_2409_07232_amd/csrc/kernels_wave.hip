@@ -108,15 +108,18 @@ __device__ __noinline__ double entry_flux(bool has_flux, const double *Mt,
   return flux_fraction_f64(c, x1) * Sm;
 }
 
-// FP32 flux of a gain entry: the target run's half slope bracket
-// hrow = (log2 m_{k+1} - log2 m_k) / 2 and guarded reciprocal im = 1 / m_k
-// come from the start of the run (see the gain loop); per entry only
-// log2(1 + Sm / m_k) remains, so that h = hrow - log2(1 + Sm / m_k) / 2 is
-// half the base-2 slope log2(m_{k+1} / (m_k + Sm)).  c = (c, 2 c ln 2).
-__device__ __forceinline__ float entry_flux_f32(float hrow, float im,
+// FP32 flux of a gain entry whose merged mass Sm lands in a target with
+// normalised mass mq, next bin's split log (le1, lm1): the slope
+// log2(m_{k+1} / (m_k + Sm)) from split logs (the exponent difference is
+// exact, so the error stays ~1e-7 absolute also where the target is nearly
+// empty and Sm dominates), carried as its half.  c = (c, 2 c ln 2).
+__device__ __forceinline__ float entry_flux_f32(float mq, int le1, float lm1,
                                                 float2 c, float Sm) {
-  float h = __builtin_fmaf(
-      __builtin_amdgcn_logf(__builtin_fmaf(Sm, im, 1.0f)), -0.5f, hrow);
+  const float den = __builtin_fmaxf(mq + Sm, 0x1p-120f);
+  int ed;
+  float fd;
+  log2_split(den, ed, fd);
+  float h = 0.5f * ((float)(le1 - ed) + (lm1 - fd));
   h = __builtin_amdgcn_fmed3f(h, kHalfLamFloor, kHalfLamCeil);
   return flux_fraction_half_f32(c.x, c.y, h) * Sm;
 }
@@ -215,7 +218,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   // bin's address is its index scaled), then the FP64 pass sums (4 SB
   // doubles from the next 8-byte boundary), then the limiter factors (FP64
   // mode, SB doubles) or the exponents of the split mass logs (FP32 mode,
-  // SB ints); wave_lds_bytes gives the total
+  // SB ints); wave_part_offset gives the total
   Real *mass = (Real *)lds;
   Real *nv = mass + SB;
   Real *lnm = nv + SB;
@@ -230,14 +233,22 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   // the next 8-byte boundary after the per-bin arrays (wave_lds_bytes)
   double *psum = (double *)(lds + wave_part_offset<F32>(SB));
 
-  // S1/S2: owned bins, FP64 total, activity (a bin's mass is recomputed
-  // from its state where needed rather than kept in registers)
-  double part = 0.0;
+  // S1/S2: owned bins, FP64 total, activity.  The numbers and bin masses
+  // of all owned bins are fetched before any is used; the bin k of
+  // q = species B + k comes from one multiply (bmagic).
+  double no[kMaxOwn], xo[kMaxOwn];
 #pragma unroll
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
-    if (q >= 0) part += st[q] * m.x[q % B];
+    const unsigned qq = q < 0 ? 0u : (unsigned)q;
+    const unsigned k = qq - __umulhi(qq, m.bmagic) * (unsigned)B;
+    no[o] = q < 0 ? 0.0 : st[qq];
+    xo[o] = m.x[k];
   }
+  double part = 0.0;
+#pragma unroll
+  for (int o = 0; o < kMaxOwn; ++o)
+    if (own[o] >= 0) part += no[o] * xo[o];
   const double Mtot = wave_sum_f64(part);
   const double thr = m.theta * Mtot;
   const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
@@ -246,18 +257,18 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
-    const double Mq = st[q] * m.x[q % B];
+    const double Mq = no[o] * xo[o];
     const bool act = Mq > 0.0 && Mq >= thr;
-    if (act) pres |= 1ull << (q / B);
+    if (act) pres |= 1ull << __umulhi((unsigned)q, m.bmagic);
     const double Mt = act ? Mq : 0.0;
     if constexpr (F32) {
       const float mq = (float)(Mt * inv);
       mass[q] = mq;
-      nv[q] = (float)((act ? st[q] : 0.0) * inv);
+      nv[q] = (float)((act ? no[o] : 0.0) * inv);
       log2_split(mq, lne[q], lnm[q]);
     } else {
       mass[q] = Mt;
-      nv[q] = act ? st[q] : 0.0;
+      nv[q] = act ? no[o] : 0.0;
       lnm[q] = log(Mt);
     }
     // the pass sums of a bin with no entries stay zero (its owner writes
@@ -314,8 +325,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         d.zero();
         int cur = -1;
         bool cur_shared = false, first_flush = true;
-        // FP32C: the current target's half slope bracket and 1 / m_k
-        float hrow = 0.0f, imq = 0.0f;
+        // FP32C: the current target's mass and its next bin's split log
+        float mq = 0.0f, lm1 = 0.0f;
+        int le1 = 0;
         // a bin's sums go to LDS directly, or (shared bin) to this lane's
         // slot: 0 for the first bin of its segment, 1 for the last
         auto flush = [&]() {
@@ -326,9 +338,12 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             psum[(1 * 2 + sl) * kWave + lane] = f.val();
             psum[(2 * 2 + sl) * kWave + lane] = d.val();
           } else {
-            P.merge(P.gain, cur, g);
-            P.merge(P.fout, cur, f);
-            if (pass == 0) P.merge(P.dneg, cur, d);
+            // the three sums read before any is written back
+            const double g0 = P.gain[cur], f0 = P.fout[cur];
+            const double d0 = pass == 0 ? P.dneg[cur] : 0.0;
+            P.gain[cur] = g0 + g.val();
+            P.fout[cur] = f0 + f.val();
+            if (pass == 0) P.dneg[cur] = d0 + d.val();
           }
           first_flush = false;
         };
@@ -354,16 +369,11 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
               d.zero();
               if constexpr (F32) {
                 // the flux flag is the target's (not its species' top bin),
-                // so it holds for the whole run; an empty target is guarded
-                // as the one-point-per-lane kernel guards it
+                // so it holds for the whole run
                 if (fl & kWFlux) {
-                  const float mg = mass[qt] + 0x1p-126f;
-                  int e0;
-                  float f0;
-                  log2_split(mg, e0, f0);
-                  hrow = 0.5f * ((float)(lne[qt + 1] - e0) + (lnm[qt + 1] - f0));
-                  const float r0 = __builtin_amdgcn_rcpf(mg);
-                  imq = __builtin_fmaf(r0, __builtin_fmaf(-mg, r0, 1.0f), r0);
+                  mq = mass[qt];
+                  le1 = lne[qt + 1];
+                  lm1 = lnm[qt + 1];
                 }
               }
             }
@@ -374,7 +384,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
                           (fl & kWSelf) != 0, xb[u], A, Bm);
             Real F;
             if constexpr (F32)
-              F = (fl & kWFlux) ? entry_flux_f32(hrow, imq, cb[u], A + Bm)
+              F = (fl & kWFlux) ? entry_flux_f32(mq, le1, lm1, cb[u], A + Bm)
                                 : 0.0f;
             else
               F = entry_flux((fl & kWFlux) != 0, mass, lnm, qt, cb[u],
@@ -561,11 +571,12 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   for (int o = 0; o < kMaxOwn; ++o) {
     const int q = own[o];
     if (q < 0) continue;
+    const int k = q - (int)__umulhi((unsigned)q, m.bmagic) * B;
     double gq = P.gain[q];
-    if (q % B != 0) gq += P.fout[q - 1];
+    if (k != 0) gq += P.fout[q - 1];
     double net = gq - P.read(P.loss, q);
     if constexpr (F32) net *= Mtot;
-    const double xq = m.x[q % B];
+    const double xq = m.x[k];
     double Mn = st[q] * xq + net;
     Mn = Mn < 0.0 ? 0.0 : Mn;
     st[q] = Mn / xq;

@@ -194,3 +194,16 @@ def test_beyond_the_largest_shape_is_refused():
     with pytest.raises(L.FsbmError) as e:
         L.FsbmCoal.from_workload(w, precision=L.FSBM_FP64)
     assert e.value.code == L.FSBM_EUNSUPPORTED
+
+
+def test_four_species_fp32c_on_a_large_sample():
+    """FP32C against the oracle on 12,000 four-species points over a whole
+    100-step call: the error tail of the compensated path shows only on
+    large samples (a slope formula that lost ~1e-6 absolute accuracy where
+    a target bin is nearly empty and the merged mass dominates passed the
+    small cases and failed here)."""
+    w = wl.config3(npoints=12000, nsteps=100)
+    ref, x, lim = run_oracle(w)
+    got, st, _ = gpu_run(w, 1)
+    assert st["kernel"] == 1
+    check(got, ref, w.N, x, 1, "species4-large", limited=lim, w=w)
