@@ -207,3 +207,70 @@ def test_four_species_fp32c_on_a_large_sample():
     got, st, _ = gpu_run(w, 1)
     assert st["kernel"] == 1
     check(got, ref, w.N, x, 1, "species4-large", limited=lim, w=w)
+
+
+def _full_size_sampled(ws, precision, label, batched, nsample=256):
+    """Whole workloads (one or several grids) advanced by one call each in
+    the benchmark's launch configuration (one multi-grid call when batched);
+    conservation and number decrease on every point through the FP64
+    totals, then nsample seeded cloudy points per grid against the oracle."""
+    L = _lib()
+    hs = [L.FsbmCoal.from_workload(w, precision=precision) for w in ws]
+    Ns = [torch.from_numpy(w.N).to("cuda") for w in ws]
+    ps = [torch.from_numpy(w.p).to("cuda") for w in ws]
+    if batched:
+        L.step_multi(hs, Ns, ps, ws[0].dt, ws[0].nsteps)
+    else:
+        for h, N, p, w in zip(hs, Ns, ps, ws):
+            h.step(N, p, w.dt, w.nsteps)
+    torch.cuda.synchronize()
+    for g, (h, N, w) in enumerate(zip(hs, Ns, ws)):
+        mb, ma, nb, na = [t.cpu().numpy() for t in h.totals()]
+        cl = mb > 0
+        assert np.max(np.abs(ma[cl] - mb[cl]) / mb[cl]) <= 1e-10
+        assert np.all(na <= nb * (1 + 1e-12))
+        idx = wl.sample_active(w, nsample, seed=11 + g)
+        got = N[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+        assert np.all(got >= 0)
+        sub = w.subset(idx)
+        ref, x, lim = run_oracle(sub)
+        check(got, ref, sub.N, x, precision, "%s-%s" % (label, w.name),
+              limited=lim, w=sub)
+        st = h.stats()
+        assert st["kernel"] == 1
+        if not batched:
+            assert st["active_points"] == int(cl.sum())
+
+
+@pytest.fixture(scope="module")
+def four_species_full():
+    return wl.config3()
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_full_size_four_species_sampled(precision, four_species_full):
+    """Four species at full size: 2^20 points, 100 steps of 2 s."""
+    _full_size_sampled([four_species_full], precision, "full4", False)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_full_size_refined_132_sampled(precision):
+    """Liquid + graupel on 132 bins at full size: 262,144 points, 100
+    steps of 2 s."""
+    _full_size_sampled([wl.config4(nbins=132)], precision, "full132", False)
+
+
+@pytest.fixture(scope="module")
+def mixed_full():
+    return wl.config5()
+
+
+def test_full_size_mixed_batch_fp32c_sampled(mixed_full):
+    """The mixed-grid batch at full size (2^22 points, 10% cloudy, 33/66/
+    132 bins) in one multi-grid FP32C call, as benchmarked."""
+    _full_size_sampled(mixed_full, 1, "full-mixed", True)
+
+
+def test_full_size_mixed_fp64_per_grid_sampled(mixed_full):
+    """The same batch in FP64, one call per grid, as benchmarked."""
+    _full_size_sampled(mixed_full, 0, "full-mixed", False)
