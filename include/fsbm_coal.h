@@ -154,6 +154,10 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
  * states; every candidate is checked against the default shape first.
  * Synchronises the stream.  The choice is kept in the handle and in the
  * cache file named by the FSBM_TUNE_CACHE environment variable, if set.
+ * The synthetic runs use the handle's workspace: until the next step,
+ * fsbm_coal_totals returns FSBM_EINVAL and fsbm_coal_get_stats reports no
+ * counters of a step call.  Errors: FSBM_EINVAL, FSBM_EHIP (allocation or
+ * runtime failure; nothing is leaked).
  */
 int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream);
 

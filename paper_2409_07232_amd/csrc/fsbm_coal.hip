@@ -61,6 +61,7 @@ struct fsbm_coal_s {
   int order = FSBM_ORDER_SIMULTANEOUS;
   double x1 = kDefaultX1, theta = 1e-30;
   std::vector<double> x, ct;
+  std::vector<double> plev;  // pressure levels (hPa), host copy
   std::vector<int> kt, product;
   // device model
   void *dmem = nullptr;
@@ -329,6 +330,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   const int B = h->B, S = h->S, L = h->L;
   const int nbr = L > 1 ? L - 1 : 1;
   const int npairs = S * (S + 1) / 2;
+  h->plev.assign(plev, plev + L);
   h->x.resize(B);
   for (int k = 0; k < B; ++k) h->x[k] = grid_mass(h->x1, h->s, k);
   h->kt.assign((size_t)B * B, -1);
@@ -979,7 +981,7 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
   // synthetic states: exponential spectra with point-dependent mean mass,
   // pressures spread over the tabulated range
   std::vector<double> N0((size_t)P * SB), p0(P);
-  const double pmax = h->L > 1 ? 1000.0 : 1000.0;
+  const double ptop = h->plev.front(), pbot = h->plev.back();
   for (int64_t pt = 0; pt < P; ++pt) {
     const double xbar = h->x[0] * pow(2.0, 3.0 + (double)(pt % 97) / 16.0);
     for (int a = 0; a < S; ++a)
@@ -989,23 +991,31 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
                             (double)(a + 1);
         N0[(size_t)pt * SB + a * B + k] = mass / xx;
       }
-    p0[pt] = pmax - 500.0 * (double)(pt % 50) / 49.0;
+    // pressures over the tabulated range, 50 levels as in a column
+    p0[pt] = ptop - (ptop - pbot) * (double)(pt % 50) / 49.0;
   }
   double *dN = nullptr, *dN0 = nullptr, *dp = nullptr;
-  HIP_TRY(h, hipMalloc(&dN, sizeof(double) * N0.size()));
-  HIP_TRY(h, hipMalloc(&dN0, sizeof(double) * N0.size()));
-  HIP_TRY(h, hipMalloc(&dp, sizeof(double) * P));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
-    hipFree(dN);
-    hipFree(dN0);
-    hipFree(dp);
+    if (dN) hipFree(dN);
+    if (dN0) hipFree(dN0);
+    if (dp) hipFree(dp);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
   };
-  if (hipMemcpy(dN0, N0.data(), sizeof(double) * N0.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(dp, p0.data(), sizeof(double) * P, hipMemcpyHostToDevice) !=
-          hipSuccess) {
+  hipError_t he = hipMalloc(&dN, sizeof(double) * N0.size());
+  if (he == hipSuccess) he = hipMalloc(&dN0, sizeof(double) * N0.size());
+  if (he == hipSuccess) he = hipMalloc(&dp, sizeof(double) * P);
+  if (he == hipSuccess)
+    he = hipMemcpy(dN0, N0.data(), sizeof(double) * N0.size(),
+                   hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(dp, p0.data(), sizeof(double) * P, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
     cleanup();
-    return FSBM_EHIP;
+    return hip_fail(h, he, "fsbm_coal_tune setup");
   }
   struct Cand {
     int spl, wpb, blocks;
@@ -1027,9 +1037,6 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
   double best_ms = 1e300;
   Cand best = cands[0];
   int rc = FSBM_OK;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
   for (size_t ci = 0; ci < cands.size() && rc == FSBM_OK; ++ci) {
     const Cand &cd = cands[ci];
     h->steps_per_launch = cd.spl;
@@ -1074,14 +1081,14 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
       best = cd;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   cleanup();
   h->flags = save_flags;
   h->steps_per_launch = best.spl;
   h->waves_per_block = best.wpb;
   h->wave_blocks = best.blocks;
   drop_graph(h);
+  // the synthetic runs leave no results of a caller's step behind
+  h->last_npoints = 0;
   if (rc == FSBM_OK) write_tune_cache(h);
   return rc;
 }
@@ -1111,6 +1118,7 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   RC_TRY(harvest_events(h));
   out->kernel_launches = h->prof_launches;
   out->kernel_ms = h->prof_ms;
+  if (h->last_npoints == 0) return FSBM_OK;  // no step since tuning
   unsigned long long c[4];
   CompactMeta meta;
   HIP_TRY(h, hipMemcpy(c, h->ws.counters, sizeof(c), hipMemcpyDeviceToHost));

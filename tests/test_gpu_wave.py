@@ -134,6 +134,11 @@ def test_autotune_keeps_results(precision, tmp_path, monkeypatch):
         w.nsteps = 20
         before, _, h = gpu_run(w, precision)
         h.tune(2048)
+        # the tuning runs leave no step results behind
+        with pytest.raises(L.FsbmError) as e:
+            h.totals()
+        assert e.value.code == L.FSBM_EINVAL
+        assert h.stats()["active_points"] == 0
         after, st, _ = gpu_run(w, precision, handle=h)
         print("tuned", w.name, st, "max|diff|=%.3e" % np.max(
             np.abs(after - before)), flush=True)
