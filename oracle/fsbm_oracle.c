@@ -20,8 +20,8 @@
  *    linearly for the point's pressure; cost quadratic in the bin count.
  *  - Sec. V-B: the collision call is made only for points whose predicate
  *    holds (here: the point holds mass).
- * Readings of what the paper leaves open are listed in the design doc; the ones
- * that shape arithmetic here are marked [R#] below.
+ * The paper leaves the collision arithmetic open; each choice taken here
+ * is a reading, marked [R#] where it shapes the arithmetic below.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  */

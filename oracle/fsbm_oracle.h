@@ -18,7 +18,8 @@
  *   S5  positivity limiter (only when some bin is over-demanded)
  *   S6  M' = M + (G - L), negative round-off clamped to 0, N' = M'/x
  *   S7  per-point mass / number before and after the call
- * Every arithmetic choice the paper leaves open is listed in the design doc.
+ * Every arithmetic choice the paper leaves open is a reading, marked [R#]
+ * where it shapes the arithmetic in fsbm_oracle.c.
  *
  * Units: N in cm^-3 per bin, x in g, K in cm^3 s^-1, p in hPa, dt in s.
  */
