@@ -116,3 +116,61 @@ def test_shapes_beyond_the_kernels_rejected_without_device_work():
     assert _create(97, 8, o) == _lib.FSBM_EUNSUPPORTED
     assert _create(513, 1, o) == _lib.FSBM_EUNSUPPORTED
     assert _create(33, 9, o) == _lib.FSBM_EINVAL
+
+
+def _create_with(nbins=8, nspecies=1, tables=None, levels=(1000.0,),
+                 product=None, **opt):
+    """fsbm_coal_create with every argument settable; returns its code.  Only
+    invalid combinations are passed, which are refused before any device
+    call."""
+    import numpy as np
+    lib = _lib.load()
+    npairs = nspecies * (nspecies + 1) // 2
+    L = len(levels)
+    if tables is None:
+        tables = np.full(npairs * L * nbins * nbins, 1e-4)
+    tables = np.ascontiguousarray(tables, dtype=np.float64)
+    plev = np.ascontiguousarray(levels, dtype=np.float64)
+    o = _lib.Opts()
+    lib.fsbm_coal_opts_default(ctypes.byref(o))
+    for k, v in opt.items():
+        setattr(o, k, v)
+    keep = None
+    if product is not None:
+        keep = (ctypes.c_int32 * len(product))(*product)
+        o.product = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p()
+    return lib.fsbm_coal_create(nbins, nspecies, tables.ctypes.data_as(dp), L,
+                                plev.ctypes.data_as(dp), ctypes.byref(o),
+                                ctypes.byref(h))
+
+
+def test_invalid_create_arguments_rejected_without_device_work():
+    """Every argument fsbm_coal_create documents as FSBM_EINVAL, one at a
+    time: sizes, pressure levels (order, finiteness), table entries
+    (negative, NaN, infinite), product map (range, symmetry, missing for
+    S > 1), grid and option values."""
+    import numpy as np
+    E = _lib.FSBM_EINVAL
+    assert _create_with(nbins=1) == E
+    assert _create_with(nspecies=0) == E
+    assert _create_with(levels=()) == E
+    assert _create_with(levels=(750.0, 1000.0)) == E       # not decreasing
+    assert _create_with(levels=(1000.0, 1000.0)) == E      # not strictly
+    assert _create_with(levels=(1000.0, np.nan)) == E
+    for v in (-1e-9, np.nan, np.inf):
+        t = np.full(8 * 8, 1e-4)
+        t[17] = v
+        assert _create_with(tables=t) == E, v
+    assert _create_with(nspecies=2) == E                   # no product map
+    assert _create_with(nspecies=2, product=[0, 1, 0, 1]) == E  # asymmetric
+    assert _create_with(nspecies=2, product=[0, 2, 2, 1]) == E  # out of range
+    assert _create_with(nspecies=2, product=[0, -1, -1, 1]) == E
+    assert _create_with(x1_g=0.0) == E
+    assert _create_with(x1_g=float("inf")) == E
+    assert _create_with(s=0) == E
+    assert _create_with(theta=-1.0) == E
+    assert _create_with(theta=float("nan")) == E
+    assert _create_with(precision=7) == E
+    assert _create_with(steps_per_launch=-1) == E

@@ -94,12 +94,19 @@ def test_degenerate_calls(precision):
     Nd = torch.zeros((0, 1, w.nbins), dtype=torch.float64, device="cuda")
     pd = torch.zeros((0,), dtype=torch.float64, device="cuda")
     h.step(Nd, pd, 2.0, 5)
-    # invalid arguments are rejected with EINVAL
-    with pytest.raises(L.FsbmError) as e:
-        Nd = torch.from_numpy(w.N.copy()).to("cuda")
-        pd = torch.from_numpy(w.p.copy()).to("cuda")
-        h.step(Nd, pd, -1.0, 5)
-    assert e.value.code == L.FSBM_EINVAL
+    # invalid arguments are rejected with EINVAL, the state untouched
+    Nd = torch.from_numpy(w.N.copy()).to("cuda")
+    pd = torch.from_numpy(w.p.copy()).to("cuda")
+    for dt, n in ((-1.0, 5), (0.0, 5), (float("nan"), 5),
+                  (float("inf"), 5), (2.0, -1)):
+        with pytest.raises(L.FsbmError) as e:
+            h.step(Nd, pd, dt, n)
+        assert e.value.code == L.FSBM_EINVAL
+    lib = L.load()
+    assert lib.fsbm_coal_step(h.handle, Nd.data_ptr(), pd.data_ptr(), -1,
+                              2.0, 5, None) == L.FSBM_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(Nd.cpu().numpy(), w.N)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -238,3 +245,28 @@ def test_handle_reused_on_fewer_points(precision, kind):
     ref, x, lim = run_oracle(sub)
     check(got, ref, sub.N, x, precision, "reuse-" + kind, limited=lim,
           w=sub)
+
+
+@pytest.mark.parametrize("bad", [-1e-3, np.nan, np.inf])
+def test_debug_checks_refuse_invalid_states(bad):
+    """With FSBM_FLAG_DEBUG_CHECKS a state holding a negative, NaN or
+    infinite number is refused with FSBM_EDOMAIN before any step runs (the
+    caller's array is left as it was); a valid state steps exactly as
+    without the flag."""
+    L = _lib()
+    w = wl.config2(nx=8, ny=8, nz=50)
+    w.nsteps = 5
+    h = L.FsbmCoal.from_workload(w, precision=1, flags=L.FLAG_DEBUG_CHECKS)
+    checked, _, _ = run_gpu(w, 1, handle=h)
+    plain, _, _ = run_gpu(w, 1)
+    assert np.array_equal(checked, plain)
+    N = w.N.copy()
+    pt = np.flatnonzero(w.cloudy())[3]
+    N[pt, 0, 5] = bad
+    Nd = torch.from_numpy(N.copy()).to("cuda")
+    pd = torch.from_numpy(w.p.copy()).to("cuda")
+    with pytest.raises(L.FsbmError) as e:
+        h.step(Nd, pd, w.dt, w.nsteps)
+    assert e.value.code == L.FSBM_EDOMAIN
+    torch.cuda.synchronize()
+    assert np.array_equal(Nd.cpu().numpy(), N, equal_nan=True)
