@@ -279,3 +279,50 @@ def test_full_size_mixed_batch_fp32c_sampled(mixed_full):
 def test_full_size_mixed_fp64_per_grid_sampled(mixed_full):
     """The same batch in FP64, one call per grid, as benchmarked."""
     _full_size_sampled(mixed_full, 0, "full-mixed", False)
+
+
+def test_multi_grid_call_refusals_and_empty_grids():
+    """fsbm_coal_step_multi refuses what one launch cannot serve (more than
+    four grids, mixed precisions, a handle twice, the sequential order, a
+    bad time step) before any work, accepts zero grids, and skips a grid
+    with no points without changing the others' results."""
+    L = _lib()
+    ws = wl.config5(npoints=3000, nsteps=4)
+    hs = [L.FsbmCoal.from_workload(w, precision=1) for w in ws]
+    Ns = [torch.from_numpy(np.array(w.N, copy=True)).to("cuda") for w in ws]
+    ps = [torch.from_numpy(np.array(w.p, copy=True)).to("cuda") for w in ws]
+
+    def refused(handles, code, dt=2.0, Nl=None, pl=None):
+        with pytest.raises(L.FsbmError) as e:
+            L.step_multi(handles, Nl or Ns[:len(handles)],
+                         pl or ps[:len(handles)], dt, 4)
+        assert e.value.code == code
+
+    extra = [L.FsbmCoal.from_workload(ws[0], precision=1) for _ in range(2)]
+    refused(hs + extra, L.FSBM_EUNSUPPORTED,
+            Nl=Ns + [Ns[0], Ns[0]], pl=ps + [ps[0], ps[0]])
+    mixed = L.FsbmCoal.from_workload(ws[1], precision=0)
+    refused([hs[0], mixed], L.FSBM_EINVAL)
+    refused([hs[0], hs[0]], L.FSBM_EINVAL, Nl=[Ns[0], Ns[0]],
+            pl=[ps[0], ps[0]])
+    w1 = wl.config2(nx=4, ny=4, nz=50)
+    seq = L.FsbmCoal.from_workload(w1, precision=0, order=L.ORDER_SEQUENTIAL)
+    n1 = torch.from_numpy(w1.N.copy()).to("cuda")
+    p1 = torch.from_numpy(w1.p.copy()).to("cuda")
+    refused([seq], L.FSBM_EUNSUPPORTED, Nl=[n1], pl=[p1])
+    refused(hs, L.FSBM_EINVAL, dt=-2.0)
+    torch.cuda.synchronize()
+    for n, w in zip(Ns, ws):
+        assert np.array_equal(n.cpu().numpy(), w.N)
+    L.step_multi([], [], [], 2.0, 4)
+    # an empty grid is skipped
+    empty = [Ns[0][:0], Ns[1], Ns[2]]
+    L.step_multi(hs, empty, [ps[0][:0], ps[1], ps[2]], ws[0].dt, 4)
+    torch.cuda.synchronize()
+    ref = [torch.from_numpy(np.array(w.N, copy=True)).to("cuda")
+           for w in ws[1:]]
+    hs2 = [L.FsbmCoal.from_workload(w, precision=1) for w in ws[1:]]
+    L.step_multi(hs2, ref, ps[1:], ws[0].dt, 4)
+    torch.cuda.synchronize()
+    for a, b in zip(Ns[1:], ref):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
