@@ -416,6 +416,15 @@ def main():
     if multi:
         cfg["launch"] = ("fp32c: one persistent launch over all grids per "
                          "fused-step group; fp64: one call per grid")
+    npts_all = sum(w.npoints for w in ws)
+
+    def rates(r):
+        # every grid point of the workload (cloud-free ones take no work)
+        # and every evaluated bin pair, per second of the timed calls
+        return {"all_points_per_s": round(npts_all * nsteps * args.steps /
+                                          r["secs"], 1),
+                "pairs_per_s": round(r["pair_evals"] / r["secs"], 1)}
+
     line = {
         "metric": "grid-point collision updates/s at 33 bins; FP32-comp vs "
                   "FP64, rel err <=1e-5",
@@ -439,6 +448,7 @@ def main():
                    "steps_per_launch": r32["stats"]["steps_per_launch"],
                    "limiter_steps": r32["limiter_steps"],
                    "fallback_steps": r32["fallback_steps"]},
+        "rates": rates(r32),
     }
     if r64 is not None:
         line["fp64"] = {"value": round(r64["updates_per_s"], 1),
@@ -446,7 +456,8 @@ def main():
                         "dtype": "f64",
                         "kernel": kernel_name(r64["stats"], 0, w0.nbins),
                         "roofline": roofline(r64, PEAK_FP64_TFLOPS),
-                        "avg_launch_ms": round(r64["kernel_avg_ms"], 4)}
+                        "avg_launch_ms": round(r64["kernel_avg_ms"], 4),
+                        "rates": rates(r64)}
     if rsq is not None:
         line["sequential"] = {
             "form": "Bott's in-place pair order, FP64",
@@ -457,7 +468,8 @@ def main():
             "roofline": roofline(rsq, PEAK_FP64_TFLOPS),
             "avg_launch_ms": round(rsq["kernel_avg_ms"], 4),
             "pair_evals": rsq["pair_evals"],
-            "capped_pairs": rsq["limiter_steps"]}
+            "capped_pairs": rsq["limiter_steps"],
+            "rates": rates(rsq)}
         if cpu is not None:
             line["sequential"]["cpu_baseline"] = cpu_sq
             line["sequential"]["parity_on_cpu_sample"] = par_sq["fp64"]
