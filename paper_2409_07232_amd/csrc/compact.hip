@@ -172,6 +172,15 @@ __global__ void __launch_bounds__(kCompactThreads)
     if (cloudy && l == bk) rank = __popcll(m & lt_mask);
   }
   __syncthreads();
+  // FP64 totals of the point (one pass over its row)
+  double m = 0.0, n = 0.0;
+  if (cloudy)
+    for (int a = 0; a < S; ++a)
+      for (int k = 0; k < B; ++k) {
+        const double v = row[a * B + k];
+        m += v * x[k];
+        n += v;
+      }
   if (cloudy) {
     int before = 0;
     for (int v = 0; v < wv; ++v) before += wave_cnt[v][l];
@@ -183,12 +192,15 @@ __global__ void __launch_bounds__(kCompactThreads)
     if (keys) {
       // sort key: bracket, top active bin, top 16 bits of the total mass
       // (positive doubles order like their bit patterns); the state is
-      // loaded after the sort
-      double mt = 0.0;
-      for (int q = 0; q < SB; ++q) mt += row[q] * x[q % B];
+      // loaded after the sort.  Keys exist for one species only (q = bin),
+      // where m is the total mass.
+      const double mt = m;
       int top = 0;
-      for (int q = 0; q < SB; ++q)
-        if (row[q] * x[q % B] >= theta * mt && row[q] > 0.0) top = q % B;
+      for (int q = SB - 1; q > 0; --q)
+        if (row[q] * x[q] >= theta * mt && row[q] > 0.0) {
+          top = q;
+          break;
+        }
       const unsigned long long bits =
           (unsigned long long)__double_as_longlong(mt);
       keys[slot] = ((unsigned)l << 24) | ((unsigned)min(top, 255) << 16) |
@@ -200,12 +212,6 @@ __global__ void __launch_bounds__(kCompactThreads)
     }
   }
   if (inside && tot) {
-    double m = 0.0, n = 0.0;
-    if (cloudy)
-      for (int q = 0; q < SB; ++q) {
-        m += row[q] * x[q % B];
-        n += row[q];
-      }
     tot[pt] = m;                     // mass before
     tot[(size_t)npoints + pt] = m;   // mass after (cloud-free: unchanged)
     tot[2 * (size_t)npoints + pt] = n;
@@ -308,13 +314,14 @@ __global__ void __launch_bounds__(kCompactThreads)
   const int SB = S * B;
   double *row = N + (int64_t)pt * SB;
   double m = 0.0, n = 0.0;
-  for (int q = 0; q < SB; ++q) {
-    const double v = aos ? state[state_index_aos(q, slot, SB)]
-                         : state[state_index(q, slot, SB)];
-    row[q] = v;
-    m += v * x[q % B];
-    n += v;
-  }
+  for (int a = 0, q = 0; a < S; ++a)
+    for (int k = 0; k < B; ++k, ++q) {
+      const double v = aos ? state[state_index_aos(q, slot, SB)]
+                           : state[state_index(q, slot, SB)];
+      row[q] = v;
+      m += v * x[k];
+      n += v;
+    }
   if (tot) {
     tot[(size_t)npoints + pt] = m;
     tot[3 * (size_t)npoints + pt] = n;
