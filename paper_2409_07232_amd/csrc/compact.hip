@@ -25,6 +25,8 @@
 //   scatter workspace -> caller's [point][species][bin] array, totals
 // Everything stays on the device, so the sequence can be captured in a
 // hipGraph without host round trips.
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace fsbm {
@@ -286,20 +288,89 @@ __global__ void __launch_bounds__(kSortThreads)
   }
 }
 
+// Tiled staging of the one-point-per-lane path (one species, at most
+// kTileBins bins): a wave moves the 64 points of one tile, each point's row
+// of the caller's array with one coalesced access (lane = bin), transposed
+// through LDS into the tile's rows (lane = slot).  A bounded grid strides
+// over the tiles, since only the device knows how many slots are filled.
+constexpr int kTileBins = 64;
+constexpr int kTilePitch = kWave + 1;  // LDS row pitch (doubles)
+constexpr int kTileGridMax = 16384;
+
 // State of every compacted point into its (sorted) slot, tiled layout.
-__global__ void __launch_bounds__(kCompactThreads)
+__global__ void __launch_bounds__(kWave)
     compact_load(const double *__restrict__ N,
                  const CompactMeta *__restrict__ meta,
                  const int *__restrict__ slot_point, int SB,
                  double *__restrict__ state) {
-  const int slot = blockIdx.x * kCompactThreads + threadIdx.x;
-  if (slot >= meta->nslots) return;
-  const int pt = slot_point[slot];
-  if (pt < 0) return;
-  const double *row = N + (int64_t)pt * SB;
-  for (int q = 0; q < SB; ++q) state[state_index(q, slot, SB)] = row[q];
+  __shared__ double tile[kTileBins * kTilePitch];
+  const int lane = threadIdx.x;
+  const int nslots = meta->nslots;
+  constexpr int kBatch = 8;  // rows whose loads are in flight together
+  for (int t0 = blockIdx.x * kWave; t0 < nslots; t0 += gridDim.x * kWave) {
+    for (int r0 = 0; r0 < kWave; r0 += kBatch) {
+      double v[kBatch];
+      int pr[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int slot = t0 + r0 + u;
+        pr[u] = slot < nslots ? slot_point[slot] : -1;
+        v[u] = (pr[u] >= 0 && lane < SB) ? N[(int64_t)pr[u] * SB + lane] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (pr[u] >= 0 && lane < SB) tile[lane * kTilePitch + r0 + u] = v[u];
+    }
+    __syncthreads();
+    const int slot = t0 + lane;
+    if (slot < nslots && slot_point[slot] >= 0)
+      for (int q = 0; q < SB; ++q)
+        state[state_index(q, slot, SB)] = tile[q * kTilePitch + lane];
+    __syncthreads();
+  }
 }
 
+// Tiled state back into the caller's array (the reverse of compact_load),
+// with each point's FP64 totals after the call (bins in ascending order).
+__global__ void __launch_bounds__(kWave)
+    scatter_tiled(double *__restrict__ N, int SB,
+                  const CompactMeta *__restrict__ meta,
+                  const int *__restrict__ slot_point,
+                  const double *__restrict__ state,
+                  const double *__restrict__ x, double *__restrict__ tot,
+                  int64_t npoints) {
+  __shared__ double tile[kTileBins * kTilePitch];
+  const int lane = threadIdx.x;
+  const int nslots = meta->nslots;
+  for (int t0 = blockIdx.x * kWave; t0 < nslots; t0 += gridDim.x * kWave) {
+    const int slot = t0 + lane;
+    const int pt = slot < nslots ? slot_point[slot] : -1;
+    if (pt >= 0) {
+      double m = 0.0, n = 0.0;
+      for (int q = 0; q < SB; ++q) {
+        const double v = state[state_index(q, slot, SB)];
+        tile[q * kTilePitch + lane] = v;
+        m += v * x[q];
+        n += v;
+      }
+      if (tot) {
+        tot[(size_t)npoints + pt] = m;
+        tot[3 * (size_t)npoints + pt] = n;
+      }
+    }
+    __syncthreads();
+    for (int r = 0; r < kWave; ++r) {
+      const int sr = t0 + r;
+      const int pr = sr < nslots ? slot_point[sr] : -1;
+      if (pr >= 0 && lane < SB)
+        N[(int64_t)pr * SB + lane] = tile[lane * kTilePitch + r];
+    }
+    __syncthreads();
+  }
+}
+
+// Workspace -> caller's array for the one-point-per-wave path (each slot's
+// bins contiguous), with each point's FP64 totals after the call.
 __global__ void __launch_bounds__(kCompactThreads)
     scatter_back(double *__restrict__ N, int S, int B,
                  const CompactMeta *__restrict__ meta,
@@ -403,9 +474,10 @@ hipError_t launch_compact_sort_load(const double *N, const CompactMeta *meta,
                      meta, keys, slot_point, wgt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;
-  hipLaunchKernelGGL(compact_load, dim3(blocks), dim3(kCompactThreads), 0, st,
-                     N, meta, slot_point, SB, state);
+  if (SB < 1 || SB > kTileBins) return hipErrorInvalidValue;
+  const int blocks = std::min((slot_cap + kWave - 1) / kWave, kTileGridMax);
+  hipLaunchKernelGGL(compact_load, dim3(blocks), dim3(kWave), 0, st, N, meta,
+                     slot_point, SB, state);
   return hipGetLastError();
 }
 
@@ -413,6 +485,15 @@ hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
                           const CompactMeta *meta, const int *slot_point,
                           const double *state, int slot_cap, const double *x,
                           double *tot, int aos, hipStream_t st) {
+  if (!aos) {
+    // tiled layout: the one-point-per-lane path (one species)
+    if (S != 1 || B > kTileBins) return hipErrorInvalidValue;
+    const int blocks =
+        std::min((slot_cap + kWave - 1) / kWave, kTileGridMax);
+    hipLaunchKernelGGL(scatter_tiled, dim3(blocks), dim3(kWave), 0, st, N, B,
+                       meta, slot_point, state, x, tot, npoints);
+    return hipGetLastError();
+  }
   const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;
   hipLaunchKernelGGL(scatter_back, dim3(blocks), dim3(kCompactThreads), 0, st,
                      N, S, B, meta, slot_point, state, slot_cap, x, tot,
