@@ -77,8 +77,20 @@ __global__ void __launch_bounds__(kCompactThreads)
       (int)max((int64_t)0, min((int64_t)kCompactThreads, npoints - p0));
   const double *__restrict__ run = N + p0 * SB;
   const unsigned total = (unsigned)np * (unsigned)SB;
-  for (unsigned e = t; e < total; e += kCompactThreads)
-    if (run[e] > 0.0) wet[__umulhi(e, magic)] = 1;
+  // four loads in flight per thread
+  for (unsigned e0 = t; e0 < total; e0 += 4 * kCompactThreads) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned e = e0 + u * kCompactThreads;
+      v[u] = e < total ? run[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned e = e0 + u * kCompactThreads;
+      if (v[u] > 0.0) wet[__umulhi(e, magic)] = 1;
+    }
+  }
   __syncthreads();
   if (t < np) {
     const bool c = wet[t] != 0;
