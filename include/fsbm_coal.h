@@ -31,7 +31,8 @@ extern "C" {
 #define FSBM_ENOMEM (-2)       /* device or host allocation failed */
 #define FSBM_EHIP (-3)         /* HIP runtime error (text kept in handle) */
 #define FSBM_EUNSUPPORTED (-4) /* valid but beyond what was compiled */
-#define FSBM_EDOMAIN (-5)      /* debug checks: negative or NaN input */
+#define FSBM_EDOMAIN (-5)      /* debug checks: negative, NaN or infinite
+                                  input */
 
 /* arithmetic of the pair loop */
 #define FSBM_FP64 0  /* every step in FP64 */
@@ -40,8 +41,10 @@ extern "C" {
                         the point's FP64 total; the FP32 amounts are summed
                         per bin in FP64 (each enters exactly, so a transfer
                         leaves and enters with the same value); FP64 final
-                        update.  Steps that need the positivity limiter run
-                        in FP64. */
+                        update.  From a point's first step that needs the
+                        positivity limiter (or, one point per wave, would
+                        drain a bin by more than half), its remaining steps
+                        of the call run in FP64. */
 
 /* update order of the pairs within a step */
 #define FSBM_ORDER_SIMULTANEOUS 0 /* every pair from the step's start state,
