@@ -16,30 +16,8 @@ namespace fsbm {
 // (s_set_gpr_idx) instead of spilling to scratch; static indices after loop
 // unrolling resolve to plain registers.
 template <int N>
-struct VecF {
-  typedef float type __attribute__((ext_vector_type(N)));
-};
-template <int N>
 struct VecD {
   typedef double type __attribute__((ext_vector_type(N)));
-};
-
-template <int B>
-struct BinsF {
-  static_assert(B >= 2 && B <= 64, "BinsF holds 2..64 bins");
-  static constexpr int N0 = B < 32 ? B : 32;
-  static constexpr int N1 = B > 32 ? B - 32 : 1;
-  typename VecF<N0>::type c0;
-  typename VecF<N1>::type c1;
-  __device__ __forceinline__ float get(int k) const {
-    return (k < 32) ? c0[k] : c1[k - 32];
-  }
-  __device__ __forceinline__ void set(int k, float v) {
-    if (k < 32)
-      c0[k] = v;
-    else
-      c1[k - 32] = v;
-  }
 };
 
 template <int B>

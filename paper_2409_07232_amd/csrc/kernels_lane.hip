@@ -247,14 +247,32 @@ __global__ void __launch_bounds__(kWave *WPB)
   add_counters(a.counters, npairs);
 }
 
+
+// FP32C: the normalised masses of a lane's bins live in the lane's column
+// of an LDS array (lane-private addresses, so no sharing and no barrier)
+// rather than in 33 VGPRs: the kernel then fits 128 VGPRs and runs 4 waves
+// per SIMD instead of 3 (8.4 KB of LDS per wave at 33 bins, 16 waves per
+// CU in 135 KB), which hides more of each pair's dependent chain.
+template <int B, int WPB>
+struct MassLds {
+  float *s;  // this thread's column: bin k at s[k * threads per block]
+  __device__ __forceinline__ float get(int k) const {
+    return s[k * (kWave * WPB)];
+  }
+  __device__ __forceinline__ void set(int k, float v) {
+    s[k * (kWave * WPB)] = v;
+  }
+};
+
 // --------------------------------------------------------- FP32C kernel
 // Same sweep and double buffering as the FP64 kernel; pair arithmetic in
 // FP32, the carried gain and the losses summed in FP64, the update FP64.
 template <int B, int WPB>
 __global__ void __launch_bounds__(kWave *WPB)
-    __attribute__((amdgpu_waves_per_eu(B <= 33 ? 3 : 2))) lane_step_f32c(
+    __attribute__((amdgpu_waves_per_eu(B <= 33 ? 4 : 2))) lane_step_f32c(
         StepArgs a) {
   constexpr int nthr = kWave * WPB;
+  __shared__ float mlds[B * nthr];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int slot = blockIdx.x * nthr + tid;
@@ -292,7 +310,8 @@ __global__ void __launch_bounds__(kWave *WPB)
     const double thr = theta * Mtot;
     const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
     uint64_t act = 0;
-    BinsF<B> m;  // active M_k / M_tot
+    MassLds<B, WPB> m;  // active M_k / M_tot (LDS column of this lane)
+    m.s = mlds + tid;
     BinsD<B> L;  // losses of bins as the smaller partner (FP64 sums)
 #pragma unroll
     for (int k = 0; k < B; ++k) {
