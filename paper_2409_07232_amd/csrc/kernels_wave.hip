@@ -627,11 +627,14 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
 // waves).  FP32C: a point whose step needs the limiter is marked pending
 // (steps of the call left) and skipped from then on; pending_only: FP64
 // steps for the marked points.
-// FP32C mode fits 128 VGPRs, i.e. 4 waves per SIMD where the point's LDS
-// allows it (four species: 3.2% faster than at 138 VGPRs and 3 waves).
+// Occupancy targets: FP32C mode fits 128 VGPRs, i.e. 4 waves per SIMD
+// where the point's LDS allows it (four species: 3.2% faster than at 138
+// VGPRs and 3 waves); FP64 mode at 168 VGPRs, 3 waves per SIMD, spills
+// some registers and is still about 20% faster than at 238 VGPRs and 2
+// waves (the entries' memory latency needs the waves).
 template <bool F32>
 __global__ void __launch_bounds__(kWave)
-    __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 2))) wave_step(WaveArgs a) {
+    __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3))) wave_step(WaveArgs a) {
   extern __shared__ unsigned char lds[];
   unsigned long long npairs = 0, nlim = 0, nfp64 = 0;
   long long total = 0;
