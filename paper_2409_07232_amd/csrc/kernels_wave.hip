@@ -631,10 +631,12 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
 // where the point's LDS allows it (four species: 3.2% faster than at 138
 // VGPRs and 3 waves); FP64 mode at 168 VGPRs, 3 waves per SIMD, spills
 // some registers and is still about 20% faster than at 238 VGPRs and 2
-// waves (the entries' memory latency needs the waves).
-template <bool F32>
+// waves (the entries' memory latency needs the waves).  Where the LDS of a
+// point already holds a CU below 3 waves per SIMD, the spills buy nothing,
+// and the FP64 build at 2 waves (no spills) runs instead.
+template <bool F32, int W>
 __global__ void __launch_bounds__(kWave)
-    __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3))) wave_step(WaveArgs a) {
+    __attribute__((amdgpu_waves_per_eu(W))) wave_step(WaveArgs a) {
   extern __shared__ unsigned char lds[];
   unsigned long long npairs = 0, nlim = 0, nfp64 = 0;
   long long total = 0;
@@ -691,12 +693,17 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
   const size_t lds = (f64 ? wave_part_offset<false>(sb)
                           : wave_part_offset<true>(sb)) +
                      kWavePartBytes;
-  if (f64)
-    hipLaunchKernelGGL(wave_step<false>, dim3(blocks), dim3(kWave), lds, st,
-                       a);
+  // 3 waves per SIMD are 12 waves per CU, sharing its 160 KB of LDS
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  if (f64 && lds * 12 <= kLdsPerCu)
+    hipLaunchKernelGGL((wave_step<false, 3>), dim3(blocks), dim3(kWave), lds,
+                       st, a);
+  else if (f64)
+    hipLaunchKernelGGL((wave_step<false, 2>), dim3(blocks), dim3(kWave), lds,
+                       st, a);
   else
-    hipLaunchKernelGGL(wave_step<true>, dim3(blocks), dim3(kWave), lds, st,
-                       a);
+    hipLaunchKernelGGL((wave_step<true, 4>), dim3(blocks), dim3(kWave), lds,
+                       st, a);
   return hipGetLastError();
 }
 
