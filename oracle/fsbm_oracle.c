@@ -23,6 +23,15 @@
  * The paper leaves the collision arithmetic open; each choice taken here
  * is a reading, marked [R#] where it shapes the arithmetic below.
  *
+ * Pins: the tests check this code against closed forms of the collection
+ * equation (constant and Golovin kernels), hand-worked steps in exact
+ * binary fractions, conservation, positivity, number decrease and the
+ * refinement ladder.  Parity unpinned: the exact form of the flux fraction
+ * [R3], the empty-neighbour guard value [R4], the off-grid rule [R6] and
+ * the species product map [R11] are fixed by these readings alone; no
+ * source in reach gives their values, and the pins above constrain the
+ * method as a whole, not these constants.
+ *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  */
 #include "fsbm_oracle.h"
