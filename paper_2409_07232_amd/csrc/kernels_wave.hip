@@ -180,7 +180,11 @@ __host__ __device__ constexpr size_t wave_part_offset(int SB) {
                    ~(size_t)7
              : (size_t)SB * 64;
 }
-constexpr size_t kWavePartBytes = 4 * 2 * kWave * sizeof(double);
+// [3 accumulators][2 slots][64 lanes]: gain, outgoing flux and dneg of the
+// gain pass; the loss pass reuses the first accumulator's slots, since its
+// writes come after the barrier that ends the gain pass's last fix-up (a
+// block without shared bins writes and reads no partial).
+constexpr size_t kWavePartBytes = 3 * 2 * kWave * sizeof(double);
 
 // Per-bin accumulators of a pass in LDS, FP64 in both modes.
 struct PassLds {
@@ -229,8 +233,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   P.dneg = P.gain + 3 * SB;
   double *sg = P.gain + 4 * SB;
   int *lne = (int *)(P.gain + 4 * SB);
-  // partial sums of shared bins: [4 accumulators][2 slots][64 lanes], from
-  // the next 8-byte boundary after the per-bin arrays (wave_lds_bytes)
+  // partial sums of shared bins: [3 accumulators][2 slots][64 lanes], from
+  // the next 8-byte boundary after the per-bin arrays (kWavePartBytes)
   double *psum = (double *)(lds + wave_part_offset<F32>(SB));
 
   // S1/S2: owned bins, FP64 total, activity.  The numbers and bin masses
@@ -459,7 +463,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
         auto flush = [&]() {
           if (cur < 0) return;
           if (cur_shared)
-            psum[(3 * 2 + (first_flush ? 0 : 1)) * kWave + lane] = lo.val();
+            psum[(0 * 2 + (first_flush ? 0 : 1)) * kWave + lane] = lo.val();
           else
             P.merge(P.loss, cur, lo);
           first_flush = false;
@@ -523,8 +527,8 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             const uint2 fx = m.wfix[fo + t];
             const int q = (int)(fx.x & 0xffffu), l0 = (int)(fx.x >> 16);
             const int l1 = (int)(fx.y & 0xffffu), s0 = (int)(fx.y >> 16);
-            double sl = psum[(3 * 2 + s0) * kWave + l0];
-            for (int l = l0 + 1; l <= l1; ++l) sl += psum[(3 * 2) * kWave + l];
+            double sl = psum[(0 * 2 + s0) * kWave + l0];
+            for (int l = l0 + 1; l <= l1; ++l) sl += psum[(0 * 2) * kWave + l];
             P.loss[q] += sl;
           }
           __syncthreads();
