@@ -68,7 +68,8 @@ def _load():
         lib.fsbm_oracle_run.argtypes = [ctypes.POINTER(_Desc), dp, dp,
                                         ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_int32, dp, dp, dp, dp, lp,
-                                        ip, ctypes.c_int32]
+                                        ip, ctypes.POINTER(ctypes.c_uint8),
+                                        ctypes.c_int32]
         lib.fsbm_oracle_run.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
@@ -151,19 +152,24 @@ class OracleModel:
         outs = [np.empty(P) for _ in range(4)] if totals else [None] * 4
         lim = ctypes.c_int64(0)
         lim_pt = np.zeros(P, dtype=np.int32)
+        lim_bins = np.zeros(N.shape, dtype=np.uint8)
         rc = _load().fsbm_oracle_run(
             ctypes.byref(self._desc), _dptr(N), _dptr(p), P, float(dt),
             int(nsteps), *[(_dptr(o) if o is not None else None)
                            for o in outs], ctypes.byref(lim),
             lim_pt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            lim_bins.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
             int(nthreads))
         if rc:
             raise ValueError("oracle rejected its input")
+        # limited_bins: [P][S][B] bool, bins the limiter scaled (sigma < 1)
+        # at some step, or (sequential form) bins a cap emptied
         if self.order == 1:
             res = {"capped_pairs": int(lim.value), "capped_per_point": lim_pt}
         else:
             res = {"limiter_steps": int(lim.value),
                    "limiter_per_point": lim_pt}
+        res["limited_bins"] = lim_bins.astype(bool)
         if totals:
             res.update({"mass_before": outs[0], "mass_after": outs[1],
                         "num_before": outs[2], "num_after": outs[3]})

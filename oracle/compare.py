@@ -18,15 +18,26 @@ def masses(N: np.ndarray, x: np.ndarray) -> np.ndarray:
     return N * x[None, None, :]
 
 
+def _floor_array(floor, shape):
+    """floor as [P][S][B]: a scalar, one value per point ([P]) or one per
+    bin ([P][S][B])."""
+    fl = np.asarray(floor, dtype=np.float64)
+    if fl.ndim == 1:
+        fl = fl[:, None, None]
+    return np.broadcast_to(fl, shape)
+
+
 def rel_bin(N_cand, N_ref, x, floor=1e-9, report=False):
-    """floor: scalar or per-point array.  With report=True also returns the
-    worst (point, species, bin) and its masses relative to the point total."""
+    """floor: scalar, per-point [P] or per-bin [P][S][B] array (fraction of
+    the point's total mass below which a bin is judged on absolute error).
+    With report=True also returns the worst (point, species, bin) and its
+    masses relative to the point total."""
     Mc = masses(np.asarray(N_cand, dtype=np.float64), x)
     Mr = masses(np.asarray(N_ref, dtype=np.float64), x)
     P = Mr.shape[0]
     tot = Mr.reshape(P, -1).sum(axis=1)
-    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
-    den = np.maximum(np.abs(Mr), (fl * tot)[:, None, None])
+    fl = _floor_array(floor, Mr.shape)
+    den = np.maximum(np.abs(Mr), fl * tot[:, None, None])
     err = np.abs(Mc - Mr)
     with np.errstate(invalid="ignore", divide="ignore"):
         r = np.where(den > 0, err / np.where(den > 0, den, 1.0),
@@ -63,11 +74,11 @@ def l1_point(N_cand, N_ref, x):
 
 
 def per_point_rel_bin(N_cand, N_ref, x, floor=1e-9):
-    """rel_bin of each point separately ([P])."""
-    P = N_ref.shape[0]
-    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
+    """rel_bin of each point separately ([P]); floor as in rel_bin."""
+    N_ref = np.asarray(N_ref, dtype=np.float64)
+    fl = _floor_array(floor, N_ref.shape)
     return np.array([rel_bin(N_cand[q:q + 1], N_ref[q:q + 1], x,
-                             floor=fl[q:q + 1]) for q in range(P)])
+                             floor=fl[q:q + 1]) for q in range(N_ref.shape[0])])
 
 
 # Conditioning at FP32 precision: the activity threshold makes the step
@@ -82,12 +93,12 @@ COND_SEEDS = (0, 1, 2)
 def unstable_points(model, N, p, dt, nsteps, ref, x, floor, tol,
                     amp=COND_AMP, seeds=COND_SEEDS):
     """model: an oracle.OracleModel; N, p: the points' inputs; ref: the
-    oracle's result for them; floor: per-point rel_bin floors.  True where
-    some seeded perturbation N (1 + amp z) moves the oracle's result by more
-    than tol (rel_bin against ref)."""
+    oracle's result for them; floor: rel_bin floors (per point or per bin).
+    True where some seeded perturbation N (1 + amp z) moves the oracle's
+    result by more than tol (rel_bin against ref)."""
     N = np.asarray(N, dtype=np.float64)
     P = N.shape[0]
-    fl = np.broadcast_to(np.asarray(floor, dtype=np.float64), (P,))
+    fl = _floor_array(floor, N.shape)
     out = np.zeros(P, dtype=bool)
     for seed in seeds:
         z = np.random.default_rng(seed).standard_normal(N.shape)

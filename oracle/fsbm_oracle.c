@@ -15,10 +15,10 @@
  *    Bott (1998, J. Atmos. Sci. 55, 2284): mass removed from both colliding
  *    bins, the merged mass placed into the bin below x_i + x_j and a fraction
  *    moved on to the next bin with an exponential sub-bin profile.
- *  - Sec. V-A, "Lookup optimization": collection kernels tabulated per pair
+ *  - Sec. VI-A, "Lookup optimization": collection kernels tabulated per pair
  *    of particle types at two (here: L) pressure levels and interpolated
  *    linearly for the point's pressure; cost quadratic in the bin count.
- *  - Sec. V-B: the collision call is made only for points whose predicate
+ *  - Sec. VI-B: the collision call is made only for points whose predicate
  *    holds (here: the point holds mass).
  * The paper leaves the collision arithmetic open; each choice taken here
  * is a reading, marked [R#] where it shapes the arithmetic below.
@@ -163,7 +163,7 @@ static void pressure_bracket(const fsbm_oracle_desc *d, double p, int *l_out,
 }
 
 /* K^{ab}_{ij}(p) = K_{l+1} + (K_l - K_{l+1}) w, the form of the lookup
-   expression shown in Sec. V-A; one level means no interpolation. */
+   expression shown in Sec. VI-A; one level means no interpolation. */
 static double kernel_entry(const fsbm_oracle_desc *d, int ab, int l, double w,
                            int i, int j) {
   int B = d->nbins, L = d->nlevels;
@@ -300,9 +300,11 @@ static void pair_pass(const ctx_t *cx, const double *N, int l, double w,
     }
 }
 
-/* One time step of one point (S1-S6).  Returns 1 if the limiter fired. */
+/* One time step of one point (S1-S6).  Returns 1 if the limiter fired.
+   lim_bins (NULL or [S*B]): set to 1 for every bin whose limiter factor
+   sigma is below 1 in this step. */
 static int step_point(const ctx_t *cx, double *N, double p, double dt,
-                      work_t *wk) {
+                      work_t *wk, unsigned char *lim_bins) {
   const int B = cx->B, S = cx->S, n = S * B;
   /* S1: masses and the point total, species then bins ascending. */
   double Mtot = 0.0;
@@ -332,7 +334,10 @@ static int step_point(const ctx_t *cx, double *N, double p, double dt,
     /* S5: sigma per bin, then a second pass with per-pair scaling. */
     for (int q = 0; q < n; ++q) {
       wk->sig[q] = 1.0;
-      if (wk->D[q] > wk->M[q]) wk->sig[q] = wk->M[q] / wk->D[q];
+      if (wk->D[q] > wk->M[q]) {
+        wk->sig[q] = wk->M[q] / wk->D[q];
+        if (lim_bins) lim_bins[q] = 1;
+      }
       wk->G[q] = wk->Ls[q] = 0.0;
     }
     pair_pass(cx, N, l, w, dt, wk, 1);
@@ -365,9 +370,10 @@ static int step_point(const ctx_t *cx, double *N, double p, double dt,
    M - (M / x) x in exact arithmetic: a rounding residue of either sign
    would keep or drop the bin from the later pairs of the step, and a pair
    (i, j) moves 2^(j-i) times bin i's mass in bin j, so residues would be
-   amplified by up to 2^(B-1).  Returns the number of capped pairs. */
+   amplified by up to 2^(B-1).  Returns the number of capped pairs; sets
+   lim_bins[q] (NULL or [B]) for every bin a cap emptied. */
 static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
-                          double *M) {
+                          double *M, unsigned char *lim_bins) {
   const int B = cx->B;
   const double *x = cx->x;
   double Mtot = 0.0;
@@ -410,16 +416,25 @@ static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
          (the same value as (M_j - Bm) + Sm without the rounding of the large
          Bm twice). */
       double Mk;
+      int emptied_i = 0, emptied_j = 0;
       if (i == j) {
+        emptied_i = hit;
         M[i] = hit ? 0.0 : M[i] - Sm;
         Mk = M[k] + Sm;
       } else if (k == j) {
+        emptied_i = hit;
         M[i] = hit ? 0.0 : M[i] - A;
         Mk = M[j] + A;
       } else {
-        M[i] = hit && C == Ni ? 0.0 : M[i] - A;
-        M[j] = hit && C == Nj ? 0.0 : M[j] - Bm;
+        emptied_i = hit && C == Ni;
+        emptied_j = hit && C == Nj;
+        M[i] = emptied_i ? 0.0 : M[i] - A;
+        M[j] = emptied_j ? 0.0 : M[j] - Bm;
         Mk = M[k] + Sm;
+      }
+      if (lim_bins) {
+        if (emptied_i) lim_bins[i] = 1;
+        if (emptied_j) lim_bins[j] = 1;
       }
       double F = 0.0;
       if (k <= B - 2) {
@@ -429,6 +444,7 @@ static int step_point_seq(const ctx_t *cx, double *N, double p, double dt,
         if (F > Mk) {
           F = Mk;
           hit = 1;
+          if (lim_bins) lim_bins[k] = 1;
         }
         M[k + 1] += F;
       }
@@ -481,7 +497,7 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     double *mass_before, double *mass_after,
                     double *num_before, double *num_after,
                     int64_t *limiter_steps, int32_t *limiter_per_point,
-                    int32_t nthreads) {
+                    unsigned char *limited_bins, int32_t nthreads) {
   if (check_desc(d) || npoints < 0 || nsteps < 0 || !(dt > 0.0) ||
       !isfinite(dt))
     return -1;
@@ -534,9 +550,12 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
         if (mass_before) mass_before[pt] = m0;
         if (num_before) num_before[pt] = n0;
         int32_t lim_pt = 0;
+        unsigned char *lb = limited_bins ? limited_bins + pt * n : NULL;
+        if (lb) memset(lb, 0, (size_t)n);
         for (int st = 0; st < nsteps; ++st)
-          lim_pt += d->order == 1 ? step_point_seq(&cx, Np, p[pt], dt, wk.M)
-                                  : step_point(&cx, Np, p[pt], dt, &wk);
+          lim_pt += d->order == 1
+                        ? step_point_seq(&cx, Np, p[pt], dt, wk.M, lb)
+                        : step_point(&cx, Np, p[pt], dt, &wk, lb);
         lim_total += lim_pt;
         if (limiter_per_point) limiter_per_point[pt] = lim_pt;
         if (mass_after || num_after) {

@@ -10,7 +10,7 @@
  * What it computes (per grid point, per time step; the paper names the
  * routine as Bott's flux method for the collision term of the bin equation,
  * Sec. III eq. (1), and describes per-point pressure-interpolated kernel
- * tables, Sec. V-A "Lookup optimization"):
+ * tables, Sec. VI-A "Lookup optimization"):
  *   S1  M = N*x, M_tot (species then bins, ascending); M_tot == 0 -> unchanged
  *   S2  bin active iff M >= theta*M_tot
  *   S3  K(p) piecewise-linear between tabulated pressure levels, clamped
@@ -52,16 +52,19 @@ typedef struct {
 /* Advance npoints independent points by nsteps steps of dt, in place.
  * N: host [npoints][S][B].  p: host [npoints].  Optional outputs (may be
  * NULL): per-point total mass / number before the first and after the last
- * step, the number of point-steps in which the limiter fired, and per point
- * the number of its steps in which it fired.  With order == 1 the last two
- * count capped pairs instead (summed over all pairs and steps).
+ * step, the number of point-steps in which the limiter fired, per point
+ * the number of its steps in which it fired, and per point and bin
+ * ([npoints][S][B] bytes) 1 where the limiter scaled that bin's demand at
+ * some step of the call (sigma < 1), else 0.  With order == 1 the counts
+ * are of capped pairs instead (summed over all pairs and steps) and the
+ * bins marked are those a cap left empty.
  * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad input. */
 int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t npoints, double dt, int32_t nsteps,
                     double *mass_before, double *mass_after,
                     double *num_before, double *num_after,
                     int64_t *limiter_steps, int32_t *limiter_per_point,
-                    int32_t nthreads);
+                    unsigned char *limited_bins, int32_t nthreads);
 
 /* Bin masses x_k, k = 0..B-1. */
 int fsbm_oracle_grid(const fsbm_oracle_desc *d, double *x);

@@ -163,6 +163,8 @@ def test_forced_limiter_example():
                      s0 * F01 + s1 * 4 * C11 * x0])
     res = om.run(N, np.array([1000.0]), dt, 1)
     assert res["limiter_steps"] == 1
+    # the bins scaled by the limiter: both over-demanded sources, not bin 2
+    assert res["limited_bins"][0, 0].tolist() == [True, True, False]
     got = N[0, 0] * x
     mt = M0 + M1
     assert np.all(got >= 0)

@@ -58,6 +58,9 @@ def test_worked_examples_exact(case):
     # every intermediate is an exact binary fraction: bit-exact
     assert [Fraction(float(v)) for v in M] == want
     assert r["capped_pairs"] == case["capped_pairs"]
+    # a cap leaves its bin exactly empty, and those are the bins marked
+    emptied = [case["capped_pairs"] > 0 and w == 0 for w in want]
+    assert r["limited_bins"][0, 0].tolist() == emptied
 
 
 def test_only_entries_with_i_le_j_are_read():
@@ -190,12 +193,13 @@ def test_well_conditioned_where_caps_fire(kernel):
     x = model_of(w, 1).grid()
     noise = np.random.default_rng(0).standard_normal(sub.N.shape)
     N1 = sub.N * (1.0 + 2e-16 * noise)
-    outs = []
+    outs, res = [], []
     for N in (sub.N.copy(), N1):
-        r = model_of(w, 1).run(N, sub.p, 4000.0, 3)
+        res.append(model_of(w, 1).run(N, sub.p, 4000.0, 3))
         outs.append(N)
-    assert r["capped_pairs"] > 0
-    floor = np.where(r["capped_per_point"] > 0, 1e-3, 1e-9)
+    assert res[0]["capped_pairs"] > 0
+    # the wider floor only on the bins a cap emptied in the reference run
+    floor = np.where(res[0]["limited_bins"], 1e-3, 1e-9)
     assert compare.rel_bin(outs[1], outs[0], x, floor=floor) < 1e-11
 
 
