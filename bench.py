@@ -10,13 +10,21 @@ steps of 2 s, scatter back.  The state evolves from call to call, like a
 model integration; inputs are resident in HBM before timing starts.
 
 Metric: grid-point collision updates per second (cloudy points x collision
-steps / time) of the FP32-compensated path; the plain FP64 path is reported
-beside it.  The roofline entry is for the dominant kernel (the collision
-step kernel), timed with HIP events on the stream it runs on.  The CPU
+steps / time) of the FP32-compensated path, timed as the library runs by
+default: each call replays its captured hipGraph on a non-default stream.
+The plain FP64 path is reported beside it.  The roofline entry is for the
+dominant kernel (the collision step kernel): a few more calls on separate
+handles launch the kernels directly and time each collision-kernel launch
+with HIP events on the stream it runs on; achieved = algorithmic flops of
+the pairs those launches evaluated / their summed duration.  The CPU
 baseline is the FP64 oracle on a bounded sample of the same workload.
 
+The default run also measures the four-species workload (2^20 points,
+liquid/ice/snow/graupel, 33 bins), the second 33-bin configuration, under
+the key "four_species".
+
 --workload selects the other measured shapes (each prints its own line with
-the same fields; the default run prints the headline line only):
+the same fields):
   four_species     2^20 points, liquid/ice/snow/graupel, 33 bins
   refined66|132|264  262,144 points, liquid + graupel, refined grids
   mixed            2^22 points, 10% cloudy, 33/66/132-bin grids in one
@@ -33,11 +41,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work per evaluated bin pair (FP32 and FP64 paths alike):
-# 24 arithmetic operations + 2 divisions + 3 transcendentals, each counted
-# as one floating-point operation.
-FLOPS_PER_PAIR = 29
+# Algorithmic work per evaluated bin pair: 24 floating-point operations
+# (interpolated kernel 2, collided masses 5, merged mass 1, neighbour ratio
+# 2, slope 2, flux fraction 4, clamps 2, flux 1, net combine 2, per-bin
+# accumulation 4; the survey of the method's cost counts these), plus 2
+# divisions and 3 transcendentals (log, exp, expm1) that are not counted as
+# flops.  OPS_PER_PAIR_ALL counts each of those once as well.
+FLOPS_PER_PAIR = 24
+OPS_PER_PAIR_ALL = 29
 FP32C_TOL = 1e-5           # rel_bin bar of the FP32C path
+FLOOR = 1e-9               # rel_bin floor (fraction of the point's mass)
+LIMITED_FLOOR = 1e-3       # floor of the bins the oracle's limiter scaled
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 
@@ -49,9 +63,6 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 TRAFFIC_SOURCES = ("kernels_lane.hip", "device_common.hpp")
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, bytes per launch, profile summary)
-    "lane_step_f32c<33>": (
-        "ed6c3a8e7abf9b33ae7222591dcef7390d7643d0b4b8214941fb912fe061b844",
-        4.305e+09, "profiles/lane_step_thunderstorm_256x256x50.md"),
 }
 
 
@@ -60,12 +71,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--profiled-calls", type=int, default=2,
+                    help="calls with per-launch HIP-event timing after the "
+                         "timed ones (kernel time of the roofline entry)")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 path beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the sequential (in-place) form, timed beside "
                          "the headline on the thunderstorm workload")
+    ap.add_argument("--no-four-species", action="store_true",
+                    help="skip the four-species entry of the default run")
     ap.add_argument("--workload", default="thunderstorm",
                     choices=["thunderstorm", "four_species", "refined66",
                              "refined132", "refined264", "mixed"])
@@ -101,73 +117,95 @@ def kernel_name(st, precision, nbins):
     return "wave_step<%s>" % ("F32" if f32 else "F64")
 
 
-def time_calls(run_once, handles, steps, warmup, nsteps):
-    """Warm up, then time `steps` calls of run_once(); the first handle
-    holds the launch timings and pair counters of a multi-grid call."""
-    import torch
-    for k in range(warmup):
-        run_once()
-        torch.cuda.synchronize()
-        log("warm-up call %d done" % (k + 1))
-    st0 = [h.stats() for h in handles]
-    pairs = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        run_once()
-        sts = [h.stats() for h in handles]   # synchronises the stream
-        pairs += sum(st["pair_evals"] for st in sts)
-        log("timed call %d done, %.1f s so far" % (k + 1,
-                                                  time.perf_counter() - t0))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = [h.stats() for h in handles]
-    launches = sum(b["kernel_launches"] - a["kernel_launches"]
-                   for a, b in zip(st0, st1))
-    kms = sum(b["kernel_ms"] - a["kernel_ms"] for a, b in zip(st0, st1))
-    active = sum(st["active_points"] for st in st1)
-    secs = t1 - t0
-    return {"secs": secs, "ms_per_step": 1e3 * secs / steps,
-            "updates_per_s": active * nsteps * steps / secs,
-            "active_points": active, "pair_evals": pairs,
-            "kernel_launches": launches, "kernel_ms": kms,
-            "kernel_avg_ms": kms / max(launches, 1),
-            "limiter_steps": sum(st["limiter_steps"] for st in st1),
-            "fallback_steps": sum(st["fp64_fallback_steps"] for st in st1),
-            "stats": st1[0]}
-
-
-def time_path(w, precision, steps, warmup, N0, p, order=0):
-    """One handle, one fsbm_coal_step per benchmark step."""
+def _handles(ws, precision, order=0, flags=0):
     from paper_2409_07232_amd import _lib as L
-    h = L.FsbmCoal.from_workload(w, precision=precision,
-                                 flags=L.FLAG_PROFILE, order=order)
-    N = N0.clone()
-    r = time_calls(lambda: h.step(N, p, w.dt, w.nsteps), [h], steps, warmup,
-                   w.nsteps)
-    h.close()
-    return r
+    return [L.FsbmCoal.from_workload(w, precision=precision, order=order,
+                                     flags=flags) for w in ws]
 
 
-def time_multi(ws, precision, steps, warmup, N0s, ps, batched):
-    """Several grids: one fsbm_coal_step_multi call (batched) or one
-    fsbm_coal_step call per grid."""
+def _runner(hs, ws, Ns, ps, batched, stream):
+    """One benchmark step: one fsbm_coal_step_multi call (batched) or one
+    fsbm_coal_step call per grid, on `stream`."""
     from paper_2409_07232_amd import _lib as L
-    hs = [L.FsbmCoal.from_workload(w, precision=precision,
-                                   flags=L.FLAG_PROFILE) for w in ws]
-    Ns = [n.clone() for n in N0s]
     if batched:
-        # the widest grid first, as the library expects its scratch to fit
         def run_once():
-            L.step_multi(hs, Ns, ps, ws[0].dt, ws[0].nsteps)
+            L.step_multi(hs, Ns, ps, ws[0].dt, ws[0].nsteps, stream=stream)
     else:
         def run_once():
             for h, N, p, w in zip(hs, Ns, ps, ws):
-                h.step(N, p, w.dt, w.nsteps)
-    r = time_calls(run_once, hs, steps, warmup, ws[0].nsteps)
+                h.step(N, p, w.dt, w.nsteps, stream=stream)
+    return run_once
+
+
+def measure(ws, precision, args, N0s, ps, batched=False, order=0,
+            label=""):
+    """Time `args.steps` calls (after `args.warmup`) through the library's
+    default path: a captured hipGraph replayed on a non-default stream.
+    Then `args.profiled_calls` more calls on separate handles with
+    FSBM_FLAG_PROFILE (direct launches, each collision-kernel launch timed
+    with HIP events on its stream), continuing from the same state, give
+    the kernel time and the pairs those launches evaluated."""
+    import torch
+    nsteps = ws[0].nsteps
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    hs = _handles(ws, precision, order)
+    Ns = [n.clone() for n in N0s]
+    torch.cuda.synchronize()
+    run_once = _runner(hs, ws, Ns, ps, batched, s)
+    for k in range(args.warmup):
+        run_once()
+        s.synchronize()
+        log("%s warm-up call %d done" % (label, k + 1))
+    pairs = exact = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        run_once()
+        sts = [h.stats() for h in hs]   # synchronises the stream
+        pairs += sum(st["pair_evals"] for st in sts)
+        exact += sum(st["exact_pair_evals"] for st in sts)
+        log("%s timed call %d done, %.1f s so far" % (
+            label, k + 1, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    sts = [h.stats() for h in hs]
+    active = sum(st["active_points"] for st in sts)
+    res = {"secs": secs, "ms_per_step": 1e3 * secs / args.steps,
+           "updates_per_s": active * nsteps * args.steps / secs,
+           "active_points": active, "pair_evals": pairs,
+           "exact_pair_evals": exact,
+           "limiter_steps": sum(st["limiter_steps"] for st in sts),
+           "fallback_steps": sum(st["fp64_fallback_steps"] for st in sts),
+           "graph_captures": sum(st["graph_captures"] for st in sts),
+           "stats": sts[0]}
     for h in hs:
         h.close()
-    return r
+    # profiled calls: the timed ones' final state, launched directly
+    from paper_2409_07232_amd import _lib as L
+    hp = _handles(ws, precision, order, flags=L.FLAG_PROFILE)
+    run_prof = _runner(hp, ws, Ns, ps, batched, s)
+    ppairs = pexact = 0
+    t0 = time.perf_counter()
+    for k in range(args.profiled_calls):
+        run_prof()
+        sts = [h.stats() for h in hp]
+        ppairs += sum(st["pair_evals"] for st in sts)
+        pexact += sum(st["exact_pair_evals"] for st in sts)
+    s.synchronize()
+    psecs = time.perf_counter() - t0
+    sts = [h.stats() for h in hp]
+    launches = sum(st["kernel_launches"] for st in sts)
+    kms = sum(st["kernel_ms"] for st in sts)
+    res.update({"prof_calls": args.profiled_calls,
+                "prof_updates_per_s": active * nsteps *
+                args.profiled_calls / max(psecs, 1e-9),
+                "prof_pair_evals": ppairs, "prof_exact_pair_evals": pexact,
+                "kernel_launches": launches, "kernel_ms": kms,
+                "kernel_avg_ms": kms / max(launches, 1)})
+    for h in hp:
+        h.close()
+    return res
 
 
 def measured_traffic(kernel):
@@ -185,11 +223,20 @@ def measured_traffic(kernel):
 
 
 def roofline(res, peak, kernel=None):
-    achieved = FLOPS_PER_PAIR * res["pair_evals"] / (res["kernel_ms"] * 1e-3)
-    achieved /= 1e12
+    """The collision kernel's algorithmic rate over its profiled launches:
+    pairs the fast kernel evaluated (the exact FP64 path's pairs left out)
+    x FLOPS_PER_PAIR / summed launch time."""
+    fast = res["prof_pair_evals"] - res["prof_exact_pair_evals"]
+    secs = max(res["kernel_ms"], 1e-9) * 1e-3
+    achieved = FLOPS_PER_PAIR * fast / secs / 1e12
+    all_ops = OPS_PER_PAIR_ALL * fast / secs / 1e12
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-            "traffic": measured_traffic(kernel) if kernel else None}
+            "traffic": measured_traffic(kernel) if kernel else None,
+            "flops_per_pair": FLOPS_PER_PAIR,
+            "ops_per_pair_incl_div_transc": OPS_PER_PAIR_ALL,
+            "frac_incl_div_transc": round(all_ops / peak, 5),
+            "pairs_per_launch": round(fast / max(res["kernel_launches"], 1))}
 
 
 def _oracle_model(w, order=0):
@@ -225,8 +272,9 @@ def cpu_baseline(ws, seconds, nsteps, order=0):
             N = np.array(sub.N, copy=True)
             res = _oracle_model(w, order).run(N, sub.p, w.dt, nsteps,
                                               nthreads=cores)
-            samples.append((idx, N, res["capped_per_point"] if order else
-                            res["limiter_per_point"]))
+            per_point = (res["capped_per_point"] if order else
+                         res["limiter_per_point"])
+            samples.append((idx, N, per_point, res["limited_bins"]))
         secs = time.perf_counter() - t0
         if secs >= seconds / 3 or all(n >= nc for n, nc in
                                       zip(npts, ncloudy)):
@@ -247,7 +295,9 @@ def cpu_baseline(ws, seconds, nsteps, order=0):
 
 def parity(ws, samples, nsteps, paths=None):
     """GPU results on the CPU-baseline sample against the oracle's (R15
-    rel_bin; points the oracle limited judged with the 1e-3 floor)."""
+    rel_bin with the 1e-9 floor; only the bins the oracle's limiter scaled
+    are judged with the 1e-3 floor).  FP32C points over the tolerance whose
+    own result is unstable at FP32 precision are counted apart."""
     import numpy as np
     import torch
 
@@ -260,7 +310,7 @@ def parity(ws, samples, nsteps, paths=None):
     for name, prec, order in paths:
         err = drift = err_all = 0.0
         n_over = n_ill = 0
-        for w, (idx, Nref, lim) in zip(ws, samples):
+        for w, (idx, Nref, lim, lim_bins) in zip(ws, samples):
             sub = w.subset(idx)
             x = wl.bin_masses(w.nbins, w.s, w.x1_g)
             h = L.FsbmCoal.from_workload(w, precision=prec, order=order)
@@ -269,13 +319,9 @@ def parity(ws, samples, nsteps, paths=None):
             h.step(N, p, w.dt, nsteps)
             got = N.cpu().numpy()
             h.close()
-            floor = np.where(lim > 0, 1e-3, 1e-9)
+            floor = np.where(lim_bins, LIMITED_FLOOR, FLOOR)
             pe = compare.per_point_rel_bin(got, Nref, x, floor)
             if prec == L.FSBM_FP32C:
-                # points over the FP32C tolerance whose own result is
-                # unstable at FP32 precision (the oracle moves by more than
-                # the tolerance under half-ulp input noise) are counted
-                # apart; every other point is held to the tolerance
                 over = np.nonzero(pe > FP32C_TOL)[0]
                 n_over += len(over)
                 if len(over):
@@ -291,6 +337,7 @@ def parity(ws, samples, nsteps, paths=None):
                      "drift": float("%.3e" % drift),
                      "limited_points": int(sum((s[2] > 0).sum()
                                                for s in samples)),
+                     "limited_bins": int(sum(s[3].sum() for s in samples)),
                      "points": int(sum(len(s[0]) for s in samples))}
         if prec == L.FSBM_FP32C:
             out[name].update({
@@ -301,10 +348,10 @@ def parity(ws, samples, nsteps, paths=None):
     return out
 
 
-def make_workloads(args):
-    """(workloads, config entry) of the selected benchmark workload."""
+def make_workloads(args, name=None):
+    """(workloads, config entry) of a benchmark workload."""
     from paper_2409_07232_amd import workloads as wl
-    name = args.workload
+    name = name or args.workload
     if name == "thunderstorm":
         ws = [wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)]
         cfg = {"workload": "thunderstorm_patch_%dx%dx%d_33bins_liquid" % (
@@ -332,6 +379,137 @@ def make_workloads(args):
     return ws, cfg
 
 
+def _rates(r, npts_all, nsteps, steps):
+    # every grid point of the workload (cloud-free ones take no work) and
+    # every evaluated bin pair, per second of the timed calls
+    return {"all_points_per_s": round(npts_all * nsteps * steps /
+                                      r["secs"], 1),
+            "pairs_per_s": round(r["pair_evals"] / r["secs"], 1)}
+
+
+def _kernel_entry(r, name, nsteps, steps):
+    return {"name": name,
+            "avg_launch_ms": round(r["kernel_avg_ms"], 4),
+            "launches_profiled": r["kernel_launches"],
+            "profiled_calls": r["prof_calls"],
+            "pair_evals_timed_calls": r["pair_evals"],
+            "exact_path_pair_evals_timed_calls": r["exact_pair_evals"],
+            "pairs_per_point_step": round(
+                r["pair_evals"] / max(1, r["active_points"] * nsteps *
+                                      steps), 1),
+            "steps_per_launch": r["stats"]["steps_per_launch"],
+            "limiter_steps": r["limiter_steps"],
+            "fallback_steps": r["fallback_steps"]}
+
+
+def _timing_entry(r):
+    return {"value_path": "captured hipGraph replayed on a non-default "
+                          "stream (the library's default)",
+            "graph_captures": r["graph_captures"],
+            "profiled_path_updates_per_s": round(r["prof_updates_per_s"],
+                                                 1)}
+
+
+def run_workload(args, name, steps, warmup, cpu_seconds, with_seq):
+    """Measure one workload: FP32C (headline), FP64, optionally the
+    sequential form, the CPU baseline and parity on its sample.  Returns
+    the entry of the JSON line (without the top-level keys)."""
+    import torch
+
+    from paper_2409_07232_amd import _lib as L
+
+    class A:
+        pass
+    a = A()
+    a.__dict__.update(vars(args))
+    a.steps, a.warmup = steps, warmup
+    log("generating workload %s" % name)
+    ws, cfg = make_workloads(args, name)
+    N0s = [torch.from_numpy(w.N).to("cuda") for w in ws]
+    ps = [torch.from_numpy(w.p).to("cuda") for w in ws]
+    multi = len(ws) > 1
+    nsteps = ws[0].nsteps
+    w0 = ws[0]
+    npts_all = sum(w.npoints for w in ws)
+    log("%s fp32c: %d warm-up + %d timed calls" % (name, warmup, steps))
+    r32 = measure(ws, L.FSBM_FP32C, a, N0s, ps, batched=multi,
+                  label=name + " fp32c")
+    log("%s fp32c %.2f ms/call, %.3e updates/s" % (
+        name, r32["ms_per_step"], r32["updates_per_s"]))
+    r64 = None
+    if not args.no_fp64:
+        r64 = measure(ws, L.FSBM_FP64, a, N0s, ps, batched=False,
+                      label=name + " fp64")
+        log("%s fp64 %.2f ms/call, %.3e updates/s" % (
+            name, r64["ms_per_step"], r64["updates_per_s"]))
+    rsq = None
+    if with_seq and not multi and w0.nspecies == 1:
+        rsq = measure(ws, L.FSBM_FP64, a, N0s, ps, order=L.ORDER_SEQUENTIAL,
+                      label=name + " sequential")
+        log("%s sequential %.2f ms/call, %.3e updates/s" % (
+            name, rsq["ms_per_step"], rsq["updates_per_s"]))
+    del N0s
+    cfg.update({"points": npts_all,
+                "cloudy_points": r32["active_points"],
+                "bins": [w.nbins for w in ws] if multi else w0.nbins,
+                "species": [w.nspecies for w in ws] if multi else
+                w0.nspecies,
+                "dt_s": w0.dt, "collision_steps_per_step": nsteps,
+                "accumulate": "fp64 (FP32 pair amounts summed per bin in "
+                              "FP64, FP64 totals and update)",
+                "parallelism": "single GPU"})
+    if multi:
+        cfg["launch"] = ("fp32c: one persistent launch over all grids per "
+                         "fused-step group; fp64: one call per grid")
+    k32 = kernel_name(r32["stats"], 1, w0.nbins)
+    ent = {"value": round(r32["updates_per_s"], 1),
+           "ms_per_step": round(r32["ms_per_step"], 4),
+           "config": cfg,
+           "roofline": roofline(r32, PEAK_FP32_TFLOPS, k32),
+           "kernel": _kernel_entry(r32, k32, nsteps, steps),
+           "timing": _timing_entry(r32),
+           "rates": _rates(r32, npts_all, nsteps, steps)}
+    if r64 is not None:
+        k64 = kernel_name(r64["stats"], 0, w0.nbins)
+        ent["fp64"] = {"value": round(r64["updates_per_s"], 1),
+                       "ms_per_step": round(r64["ms_per_step"], 4),
+                       "dtype": "f64",
+                       "roofline": roofline(r64, PEAK_FP64_TFLOPS, k64),
+                       "kernel": _kernel_entry(r64, k64, nsteps, steps),
+                       "timing": _timing_entry(r64),
+                       "rates": _rates(r64, npts_all, nsteps, steps)}
+    if rsq is not None:
+        ksq = kernel_name(rsq["stats"], 0, w0.nbins)
+        ent["sequential"] = {
+            "form": "Bott's in-place pair order, FP64",
+            "value": round(rsq["updates_per_s"], 1),
+            "unit": "grid-point collision updates/s",
+            "ms_per_step": round(rsq["ms_per_step"], 4), "dtype": "f64",
+            "roofline": roofline(rsq, PEAK_FP64_TFLOPS, ksq),
+            "kernel": _kernel_entry(rsq, ksq, nsteps, steps),
+            "capped_pairs": rsq["limiter_steps"],
+            "timing": _timing_entry(rsq),
+            "rates": _rates(rsq, npts_all, nsteps, steps)}
+    if not args.no_cpu_baseline:
+        csteps = args.cpu_steps or nsteps
+        log("%s cpu baseline (oracle), about %.0f s" % (name, cpu_seconds))
+        cpu, samples = cpu_baseline(ws, cpu_seconds, csteps)
+        log("%s cpu %.3e updates/s on %d cores (%s)" % (
+            name, cpu["value"], cpu["cores"], cpu["sample"]))
+        ent["cpu_baseline"] = cpu
+        ent["parity_on_cpu_sample"] = parity(ws, samples, csteps)
+        if rsq is not None:
+            log("%s cpu baseline of the sequential form, about %.0f s" % (
+                name, cpu_seconds / 3))
+            cpu_sq, samples_sq = cpu_baseline(ws, cpu_seconds / 3, csteps,
+                                              order=1)
+            ent["sequential"]["cpu_baseline"] = cpu_sq
+            ent["sequential"]["parity_on_cpu_sample"] = parity(
+                ws, samples_sq, csteps,
+                paths=(("fp64", L.FSBM_FP64, 1),))["fp64"]
+    return ent
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -355,127 +533,29 @@ def main():
                           n * 8, "dispatches": 3}), flush=True)
         return
     L.load()
-    log("generating workload %s" % args.workload)
-    ws, cfg = make_workloads(args)
-    N0s = [torch.from_numpy(w.N).to("cuda") for w in ws]
-    ps = [torch.from_numpy(w.p).to("cuda") for w in ws]
-    multi = len(ws) > 1
-    log("timing fp32c: %d warmup + %d steps" % (args.warmup, args.steps))
-    if multi:
-        r32 = time_multi(ws, L.FSBM_FP32C, args.steps, args.warmup, N0s, ps,
-                         batched=True)
-    else:
-        r32 = time_path(ws[0], L.FSBM_FP32C, args.steps, args.warmup, N0s[0],
-                        ps[0])
-    log("fp32c %.2f ms/step, %.3e updates/s" % (r32["ms_per_step"],
-                                               r32["updates_per_s"]))
-    r64 = None
-    if not args.no_fp64:
-        log("timing fp64" + (" (per-grid launches)" if multi else ""))
-        if multi:
-            r64 = time_multi(ws, L.FSBM_FP64, args.steps, args.warmup, N0s,
-                             ps, batched=False)
-        else:
-            r64 = time_path(ws[0], L.FSBM_FP64, args.steps, args.warmup,
-                            N0s[0], ps[0])
-        log("fp64 %.2f ms/step, %.3e updates/s" % (r64["ms_per_step"],
-                                                  r64["updates_per_s"]))
-    rsq = None
-    if not args.no_sequential and not multi and ws[0].nspecies == 1:
-        log("timing the sequential form (fp64)")
-        rsq = time_path(ws[0], L.FSBM_FP64, args.steps, args.warmup, N0s[0],
-                        ps[0], order=L.ORDER_SEQUENTIAL)
-        log("sequential %.2f ms/step, %.3e updates/s" % (
-            rsq["ms_per_step"], rsq["updates_per_s"]))
-    del N0s
-    nsteps = ws[0].nsteps
-    cpu = par = None
-    if not args.no_cpu_baseline:
-        csteps = args.cpu_steps or nsteps
-        log("cpu baseline (oracle), about %.0f s" % args.cpu_seconds)
-        cpu, samples = cpu_baseline(ws, args.cpu_seconds, csteps)
-        log("cpu %.3e updates/s on %d cores (%s)" % (cpu["value"],
-                                                    cpu["cores"],
-                                                    cpu["sample"]))
-        par = parity(ws, samples, csteps)
-        if rsq is not None:
-            log("cpu baseline of the sequential form (oracle), about %.0f s"
-                % (args.cpu_seconds / 3))
-            cpu_sq, samples_sq = cpu_baseline(ws, args.cpu_seconds / 3,
-                                              csteps, order=1)
-            par_sq = parity(ws, samples_sq, csteps,
-                            paths=(("fp64", L.FSBM_FP64, 1),))
-    w0 = ws[0]
-    cfg.update({"points": sum(w.npoints for w in ws),
-                "cloudy_points": r32["active_points"],
-                "bins": [w.nbins for w in ws] if multi else w0.nbins,
-                "species": [w.nspecies for w in ws] if multi else
-                w0.nspecies,
-                "dt_s": w0.dt, "collision_steps_per_step": nsteps,
-                "parallelism": "single GPU"})
-    if multi:
-        cfg["launch"] = ("fp32c: one persistent launch over all grids per "
-                         "fused-step group; fp64: one call per grid")
-    npts_all = sum(w.npoints for w in ws)
-
-    def rates(r):
-        # every grid point of the workload (cloud-free ones take no work)
-        # and every evaluated bin pair, per second of the timed calls
-        return {"all_points_per_s": round(npts_all * nsteps * args.steps /
-                                          r["secs"], 1),
-                "pairs_per_s": round(r["pair_evals"] / r["secs"], 1)}
-
+    ent = run_workload(args, args.workload, args.steps, args.warmup,
+                       args.cpu_seconds, not args.no_sequential)
     line = {
         "metric": "grid-point collision updates/s at 33 bins; FP32-comp vs "
                   "FP64, rel err <=1e-5",
-        "value": round(r32["updates_per_s"], 1),
+        "value": ent.pop("value"),
         "unit": "grid-point collision updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(r32["ms_per_step"], 4),
+        "ms_per_step": ent.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": cfg,
-        "roofline": roofline(r32, PEAK_FP32_TFLOPS,
-                             kernel_name(r32["stats"], 1, w0.nbins)),
-        "kernel": {"name": kernel_name(r32["stats"], 1, w0.nbins),
-                   "avg_launch_ms": round(r32["kernel_avg_ms"], 4),
-                   "launches": r32["kernel_launches"],
-                   "pair_evals": r32["pair_evals"],
-                   "pairs_per_point_step": round(
-                       r32["pair_evals"] / max(1, r32["active_points"] *
-                                               nsteps * args.steps), 1),
-                   "flops_per_pair": FLOPS_PER_PAIR,
-                   "steps_per_launch": r32["stats"]["steps_per_launch"],
-                   "limiter_steps": r32["limiter_steps"],
-                   "fallback_steps": r32["fallback_steps"]},
-        "rates": rates(r32),
+        "config": ent.pop("config"),
+        "roofline": ent.pop("roofline"),
     }
-    if r64 is not None:
-        line["fp64"] = {"value": round(r64["updates_per_s"], 1),
-                        "ms_per_step": round(r64["ms_per_step"], 4),
-                        "dtype": "f64",
-                        "kernel": kernel_name(r64["stats"], 0, w0.nbins),
-                        "roofline": roofline(r64, PEAK_FP64_TFLOPS),
-                        "avg_launch_ms": round(r64["kernel_avg_ms"], 4),
-                        "rates": rates(r64)}
-    if rsq is not None:
-        line["sequential"] = {
-            "form": "Bott's in-place pair order, FP64",
-            "value": round(rsq["updates_per_s"], 1),
-            "unit": "grid-point collision updates/s",
-            "ms_per_step": round(rsq["ms_per_step"], 4), "dtype": "f64",
-            "kernel": kernel_name(rsq["stats"], 0, w0.nbins),
-            "roofline": roofline(rsq, PEAK_FP64_TFLOPS),
-            "avg_launch_ms": round(rsq["kernel_avg_ms"], 4),
-            "pair_evals": rsq["pair_evals"],
-            "capped_pairs": rsq["limiter_steps"],
-            "rates": rates(rsq)}
-        if cpu is not None:
-            line["sequential"]["cpu_baseline"] = cpu_sq
-            line["sequential"]["parity_on_cpu_sample"] = par_sq["fp64"]
-    if cpu is not None:
-        line["cpu_baseline"] = cpu
-        line["parity_on_cpu_sample"] = par
+    if "cpu_baseline" in ent:
+        line["cpu_baseline"] = ent.pop("cpu_baseline")
+    line.update(ent)
+    if args.workload == "thunderstorm" and not args.no_four_species:
+        # the second 33-bin configuration: fewer calls (each is seconds)
+        fs = run_workload(args, "four_species", min(args.steps, 2), 1,
+                          min(args.cpu_seconds, 8.0), False)
+        fs["dtype"] = "f32"
+        line["four_species"] = fs
     line["context"] = {
         "paper": "2.08x whole-WRF speedup, 16 A100 vs 16 EPYC cores "
                  "(CONUS-12km); collision kernel 29.11 ms per call on one "

@@ -4,10 +4,10 @@
  * The library advances the bin spectra of many independent grid points by
  * the collision-coalescence term of the bin equation (Sec. III, eq. (1)),
  * solved with Bott's flux method (the routine the paper offloads, Sec. III
- * and Sec. V), with the collection kernels of every pair of particle types
+ * and Sec. VI), with the collection kernels of every pair of particle types
  * tabulated at a few pressure levels and interpolated linearly for each
- * point's pressure (Sec. V-A, "Lookup optimization"), and with the work
- * restricted to cloudy points (the predicate array of Sec. V-B).
+ * point's pressure (Sec. VI-A, "Lookup optimization"), and with the work
+ * restricted to cloudy points (the predicate array of Sec. VI-B).
  *
  * All functions return 0 on success or a negative FSBM_E* code; none aborts
  * or throws.  fsbm_coal_strerror() turns a code into text; the handle keeps
@@ -94,7 +94,7 @@ typedef struct {
 void fsbm_coal_opts_default(fsbm_coal_opts *opts);
 
 /*
- * Create a handle for one bin grid and species set (Sec. V-A: collection
+ * Create a handle for one bin grid and species set (Sec. VI-A: collection
  * kernels per particle-type pair at pressure levels).
  *  nbins          B >= 2 bins per species (mass grid x_k = x1 2^(k/s))
  *  nspecies       S in [1, 8]
@@ -119,7 +119,7 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
 
 /*
  * Advance npoints grid points by nsteps collision steps of dt_s seconds
- * (Sec. V-B: the offloaded collision loop over all points whose predicate
+ * (Sec. VI-B: the offloaded collision loop over all points whose predicate
  * holds; here a point takes part iff it holds mass).
  *  N       device, FP64, C-contiguous [npoints][S][B], updated in place
  *  p_hpa   device, FP64, [npoints] pressure of each point
@@ -176,7 +176,8 @@ int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
 typedef struct {
   int64_t active_points;  /* cloudy points in the last step call */
   int64_t pair_evals;     /* bin pairs evaluated (both bins active, merged
-                             mass inside the grid), summed over points and
+                             mass inside the grid, kernel entry nonzero at
+                             some tabulated level), summed over points and
                              steps of the last call */
   int64_t limiter_steps;  /* point-steps where the positivity limiter ran;
                              sequential order: pairs at which a positivity
@@ -197,6 +198,14 @@ typedef struct {
   int32_t kernel_launches; /* FSBM_FLAG_PROFILE: collision-kernel launches
                               timed since the handle was created */
   double kernel_ms;        /* FSBM_FLAG_PROFILE: their summed duration */
+  int64_t exact_pair_evals; /* the part of pair_evals evaluated on the
+                               exact FP64 path of points that left the fast
+                               kernel (see fp64_fallback_steps) */
+  int64_t graph_captures;  /* hipGraphs this handle has captured since it
+                              was created: a call replays the handle's
+                              cached graph only while the call's
+                              arguments, launch shape and the workspaces
+                              of every handle in it are unchanged */
 } fsbm_coal_stats;
 
 /* Counters of the last step call.  Synchronises that call's stream. */

@@ -68,7 +68,9 @@ class Stats(ctypes.Structure):
                 ("steps_per_launch", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double),
+                ("exact_pair_evals", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64)]
 
 
 _lib = None

@@ -2,7 +2,7 @@
 // the step kernels.
 //
 // The paper isolates the collision call behind a per-point predicate array
-// (Sec. V-B) and notes that cloud-free cells need far less work (Sec. VII).
+// (Sec. VI-B) and notes that cloud-free cells need far less work (Sec. VIII).
 // Here a point is cloudy iff it holds mass; collisions neither create nor
 // remove a point's mass, so the cloudy set is fixed for the whole call and
 // is built once per call:
@@ -37,7 +37,7 @@ constexpr int kCompactThreads = 256;
 
 // Pressure bracket and weight of level l: clamp p into the tabulated range,
 // take the first level pair with p_l >= p >= p_{l+1}, w is the weight of
-// level l (linear interpolation, Sec. V-A).
+// level l (linear interpolation, Sec. VI-A).
 __device__ __forceinline__ void bracket_of(const double *plev, int L,
                                            double p, int &l, double &w) {
   if (L == 1) {

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -35,19 +36,28 @@ constexpr int kDefaultSteps = 10;
 // SIMD several times over (256 CUs x 4 SIMDs x 8 waves)
 constexpr int kDefaultWaveBlocks = 8192;
 
+// Generation numbers of device allocations baked into captured graphs: a
+// handle takes a new one at create and whenever its workspace is
+// reallocated, so a graph that holds another handle's pointers (multi-grid
+// calls) is never replayed after that handle's memory changed, even if a
+// new handle reuses the old one's address.
+std::atomic<uint64_t> g_generation{0};
+
 // Arguments a captured graph depends on.
 struct GraphKey {
   std::vector<const void *> ptrs;  // N and p of every grid
   std::vector<int64_t> npts;
   std::vector<const void *> handles;
+  std::vector<uint64_t> gens;      // generation of every grid's handle
   double dt = 0.0;
   int nsteps = -1;
   void *stream = nullptr;
   int spl = 0, wpb = 0, blocks = 0;
   bool operator==(const GraphKey &o) const {
     return ptrs == o.ptrs && npts == o.npts && handles == o.handles &&
-           dt == o.dt && nsteps == o.nsteps && stream == o.stream &&
-           spl == o.spl && wpb == o.wpb && blocks == o.blocks;
+           gens == o.gens && dt == o.dt && nsteps == o.nsteps &&
+           stream == o.stream && spl == o.spl && wpb == o.wpb &&
+           blocks == o.blocks;
   }
 };
 
@@ -75,6 +85,8 @@ struct fsbm_coal_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey;
+  uint64_t gen = 0;           // see g_generation
+  int64_t graph_captures = 0; // graphs captured by this handle
   // profiling (FSBM_FLAG_PROFILE): event pairs around collision launches
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_used = 0;
@@ -185,12 +197,20 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
   // is also the pair's target has no separate loss: its merged net is
   // formed on the gain side)
   std::vector<std::vector<Pair>> T(SB), Lq(SB);
-  for (int a = 0; a < S; ++a)
-    for (int b = a; b < S; ++b)
+  // a pair whose kernel entry is zero at every level collides nothing
+  auto zero_kernel = [&](int ab, int i, int j) {
+    for (int br = 0; br < nbr; ++br) {
+      const size_t t = (((size_t)ab * nbr + br) * B * B + (size_t)i * B + j) * 2;
+      if (Kd[t] != 0.0 || Kd[t + 1] != 0.0) return false;
+    }
+    return true;
+  };
+  for (int a = 0, ab = 0; a < S; ++a)
+    for (int b = a; b < S; ++b, ++ab)
       for (int i = 0; i < B; ++i)
         for (int j = (a == b ? i : 0); j < B; ++j) {
           const int k = h->kt[(size_t)i * B + j];
-          if (k < 0) continue;
+          if (k < 0 || zero_kernel(ab, i, j)) continue;
           const int P = h->product[(size_t)a * S + b];
           const int qt = P * B + k, qa = a * B + i, qb = b * B + j;
           T[qt].push_back({a, i, b, j, false});
@@ -402,6 +422,13 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       ctfT[((size_t)j * B + i) * 2] = cf;
       ctfT[((size_t)j * B + i) * 2 + 1] = 2.0f * (cf * kLn2f);
     }
+  // rows of species pair 0: entries [i][j], i <= j, nonzero at some level
+  std::vector<unsigned long long> nzT(B, 0ull);
+  for (int j = 0; j < B && j < 64; ++j)
+    for (int i = 0; i <= j; ++i)
+      for (int l = 0; l < L; ++l)
+        if (tables[(size_t)l * B * B + (size_t)i * B + j] != 0.0)
+          nzT[j] |= 1ull << i;
   WaveTables wt;
   const bool wave_ok = S * B <= kWave * kMaxOwn;
   if (wave_ok) RC_TRY(build_wave_tables(h, Kd, Kf, xf, ctf, nbr, wt));
@@ -438,6 +465,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
       {wt.blk.data(), sizeof(int) * wt.blk.size(), 0},
       {wt.fixb.data(), sizeof(int) * wt.fixb.size(), 0},
       {wt.fix.data(), sizeof(uint2) * wt.fix.size(), 0},
+      {nzT.data(), sizeof(unsigned long long) * B, 0},
   };
   size_t off = 0;
   for (auto &p : parts) {
@@ -488,6 +516,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.wblk = (const int *)at(23);
   m.wfixb = (const int *)at(24);
   m.wfix = (const uint2 *)at(25);
+  m.nzT = (const unsigned long long *)at(26);
   return FSBM_OK;
 }
 
@@ -526,7 +555,7 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   const size_t o_bc = take(sizeof(int) * (size_t)nblocks * kMaxBuckets);
   const size_t o_bo = take(sizeof(int) * (size_t)nblocks * kMaxBuckets);
   const size_t o_meta = take(sizeof(CompactMeta));
-  const size_t o_cnt = take(sizeof(unsigned long long) * 4);
+  const size_t o_cnt = take(sizeof(unsigned long long) * kNumCounters);
   const size_t o_pend = take(sizeof(int) * cap);
   const size_t o_keys = h->lane ? take(sizeof(unsigned) * cap) : 0;
   const size_t o_wet = take((size_t)npoints);
@@ -534,6 +563,9 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   if (h->wmem) hipFree(h->wmem);
   h->wmem = nullptr;
   h->wpoints = -1;
+  // every graph holding the old workspace (this handle's or another
+  // handle's multi-grid graph) is stale from here on
+  h->gen = ++g_generation;
   hipError_t e = hipMalloc(&h->wmem, off);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -620,7 +652,7 @@ int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
                      int64_t npoints, bool aos, hipStream_t st) {
   const DevModel &m = h->dm;
   DevWork &w = h->ws;
-  HIP_TRY(h, launch_zero_u64(w.counters, 4, st));
+  HIP_TRY(h, launch_zero_u64(w.counters, kNumCounters, st));
   HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
                                   w.block_counts, w.cloudy, h->nblocks, st));
   HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, h->nblocks,
@@ -751,6 +783,7 @@ int run_call(const Call &c, void *stream) {
     key.ptrs.push_back(c.p[g]);
     key.npts.push_back(c.npts[g]);
     key.handles.push_back(c.hs[g]);
+    key.gens.push_back(c.hs[g]->gen);
   }
   key.dt = c.dt;
   key.nsteps = c.nsteps;
@@ -777,6 +810,7 @@ int run_call(const Call &c, void *stream) {
       return hip_fail(h0, ei, "hipGraphInstantiate");
     }
     h0->gkey = key;
+    h0->graph_captures++;
   }
   HIP_TRY(h0, hipGraphLaunch(h0->gexec, st));
   return FSBM_OK;
@@ -888,6 +922,7 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
   h->lane = lane_kernel_supported(nbins, nspecies, o.s) &&
             !(o.flags & FSBM_FLAG_FORCE_WAVE);
   h->order = o.order;
+  h->gen = ++g_generation;
   read_tune_cache(h);
   const int rc = build_model(h, kernel_tables, p_levels_hpa);
   if (rc != FSBM_OK) {
@@ -1113,13 +1148,14 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   out->kernel = kernel_id(h);
   out->steps_per_launch = steps_per_launch(h);
   out->waves_per_block = h->lane ? waves_per_block(h) : 1;
+  out->graph_captures = h->graph_captures;
   if (h->wpoints < 0) return FSBM_OK;
   HIP_TRY(h, hipStreamSynchronize(h->last_stream));
   RC_TRY(harvest_events(h));
   out->kernel_launches = h->prof_launches;
   out->kernel_ms = h->prof_ms;
   if (h->last_npoints == 0) return FSBM_OK;  // no step since tuning
-  unsigned long long c[4];
+  unsigned long long c[kNumCounters];
   CompactMeta meta;
   HIP_TRY(h, hipMemcpy(c, h->ws.counters, sizeof(c), hipMemcpyDeviceToHost));
   HIP_TRY(h, hipMemcpy(&meta, h->ws.meta, sizeof(meta),
@@ -1128,6 +1164,7 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   out->pair_evals = (int64_t)c[0];
   out->limiter_steps = (int64_t)c[1];
   out->fp64_fallback_steps = (int64_t)c[2];
+  out->exact_pair_evals = (int64_t)c[4];
   return FSBM_OK;
 }
 

@@ -20,6 +20,7 @@ constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
 constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
 constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
+constexpr int kNumCounters = 5;    // device counters of a step call
 // Empty-neighbour guard of the flux fraction: x1 >= ln(1e-60).
 constexpr double kX1Floor = -138.15510557964274;
 
@@ -47,6 +48,10 @@ struct DevModel {
   const float *KfT;
   const double *ctT;
   const float *ctfT;  // [j][i][2]: FP32 Courant number c and 2 (c * kLn2f)
+  // species pair 0, row j: bit i (i <= j) set iff the kernel entry [i][j]
+  // is nonzero at some tabulated level; a pair whose entry is zero at every
+  // level collides nothing (C = 0) and is neither evaluated nor counted
+  const unsigned long long *nzT;  // [B]
   // one-point-per-wave kernel: bins of each lane's per-bin work ([64]
   // [kMaxOwn], -1 padded) and two streams of pair entries, gain entries
   // (grouped by the bin the pair lands in) and loss entries (grouped by the
@@ -120,8 +125,10 @@ struct DevWork {
   int *pending;          // [slot_cap] steps of the call left for the exact
                          // FP64 path (0 = point still on the fast path)
   unsigned char *cloudy;  // [npoints] 1 iff the point holds mass
-  unsigned long long *counters;  // [4]: pair evals, limiter, fallback,
-                                 // work-queue position of the wave kernel
+  unsigned long long *counters;  // [kNumCounters]: pair evals, limiter,
+                                 // fallback steps, work-queue position of
+                                 // the wave kernel, pair evals of the exact
+                                 // FP64 path (also in the first)
 };
 
 // One grid of a one-point-per-wave launch (a call may cover several grids).

@@ -64,12 +64,15 @@ __device__ __forceinline__ void add_counters(unsigned long long *counters,
 }
 
 // Pairs a lane evaluates in row j: bin j active, each active i < j, plus the
-// self pair while its merged mass stays on the grid.
+// self pair while its merged mass stays on the grid, all with a kernel entry
+// that is nonzero at some level (row mask nz).
 template <int B>
-__device__ __forceinline__ unsigned row_pairs(uint64_t act, int j) {
+__device__ __forceinline__ unsigned row_pairs(uint64_t act, uint64_t nz,
+                                              int j) {
   if (!((act >> j) & 1ull)) return 0u;
-  const uint64_t below = (j == 0) ? 0ull : (act & (~0ull >> (64 - j)));
-  return (unsigned)__popcll(below) + ((j + 1 <= B - 1) ? 1u : 0u);
+  const uint64_t below = (j == 0) ? 0ull : (act & nz & (~0ull >> (64 - j)));
+  return (unsigned)__popcll(below) +
+         ((j + 1 <= B - 1 && ((nz >> j) & 1ull)) ? 1u : 0u);
 }
 
 __device__ __forceinline__ bool bit_of(uint32_t lo, uint32_t hi, int k) {
@@ -169,8 +172,11 @@ __global__ void __launch_bounds__(kWave *WPB)
       Nnext = sb[j * kWave + lane];
       double gj = 0.0;  // gain of bin j from row j
       if (bit_of(uni_lo, uni_hi, j)) {
-        // columns to visit: i < j with bin i active in some lane
-        const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+        // columns to visit: i < j with bin i active in some lane and a
+        // kernel entry that is not zero at every level
+        const uint64_t nz = ldc(a.m.nzT + j);
+        const uint64_t below_mask =
+            ((j == 0) ? 0ull : (~0ull >> (64 - j))) & nz;
         const uint32_t cl = uni_lo & (uint32_t)below_mask;
         const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
         const double Mtj = Mt.get(j);
@@ -204,7 +210,7 @@ __global__ void __launch_bounds__(kWave *WPB)
         }
         // self pair: 2 x_j = x_{j+1} exactly, no flux; off grid for j = B-1
         double self2 = 0.0;
-        if (j + 1 <= B - 1) {
+        if (j + 1 <= B - 1 && ((nz >> j) & 1ull)) {
           const double *e = Kj + j * 2;
           const double K = fma(ldc(e + 1), w, ldc(e));
           const double A = 0.5 * ((qj * K) * Mtj);
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(kWave *WPB)
         flag = flag || (Mtj > 0.0 && demand > Mtj);
         gj = 0.0 + (netj - self2);
         if (j + 1 <= B - 1) g += fout + self2;
-        step_pairs += row_pairs<B>(act, j);
+        step_pairs += row_pairs<B>(act, nz, j);
       }
       if (j + 1 <= B - 1) finish(j + 1, g, Nj1);
       g = gj;
@@ -351,7 +357,10 @@ __global__ void __launch_bounds__(kWave *WPB)
       if (bit_of(uni_lo, uni_hi, j)) {
         double fs = 0.0;     // flux leaving bin j for j+1
         float self2 = 0.0f;  // self-pair mass, bin j -> j+1
-        const uint64_t below_mask = (j == 0) ? 0ull : (~0ull >> (64 - j));
+        // columns: active in some lane, kernel entry nonzero at some level
+        const uint64_t nz = ldc(a.m.nzT + j);
+        const uint64_t below_mask =
+            ((j == 0) ? 0ull : (~0ull >> (64 - j))) & nz;
         const uint32_t cl = uni_lo & (uint32_t)below_mask;
         const uint32_t ch = uni_hi & (uint32_t)(below_mask >> 32);
         const float mj = m.get(j);
@@ -426,7 +435,7 @@ __global__ void __launch_bounds__(kWave *WPB)
           }
         }
         // self pair: transfer 2A from bin j to bin j+1 (exact hit, no flux)
-        if (j + 1 <= B - 1) {
+        if (j + 1 <= B - 1 && ((nz >> j) & 1ull)) {
           const float *e = Kj + j * 2;
           const float tK = __builtin_fmaf(ldc(e + 1), tjw, tj * ldc(e));
           const float A = 0.5f * (tK * mj);
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(kWave *WPB)
         // passes on to j+1
         gj = as - out;
         if (j + 1 <= B - 1) g += out;
-        step_pairs += row_pairs<B>(act, j);
+        step_pairs += row_pairs<B>(act, nz, j);
       }
       if (j + 1 <= B - 1) finish(j + 1, g, Nj1);
       g = gj;
@@ -490,6 +499,7 @@ __global__ void __launch_bounds__(64) slow_steps(StepArgs a) {
           a.wgt[slot], br, a.dt, &pairs);
     a.pending[slot] = 0;
     atomicAdd(&a.counters[0], pairs);
+    atomicAdd(&a.counters[4], pairs);
     if (lim) atomicAdd(&a.counters[1], lim);
     atomicAdd(&a.counters[2], (unsigned long long)n);
   }

@@ -89,9 +89,11 @@ __global__ void __launch_bounds__(kWave *WPB)
       const double *ci = ctab + (size_t)i * B;
       const double ixi = ldc(ixg + i);
       // self pair: C = dt K N_i^2 / 2, at most N_i / 2; 2 C x_i moves to
-      // bin i+1 (an exact hit: no flux)
+      // bin i+1 (an exact hit: no flux); a kernel entry that is zero at
+      // every level collides nothing
       double gain = 0.0;
-      {
+      const uint64_t nzi = ldc(a.m.nzT + i);
+      if ((nzi >> i) & 1ull) {
         const bool act = mi > 0.0 && mi >= thr;
         const double K = fma(ldc(Ki + i * 2 + 1), w, ldc(Ki + i * 2));
         const double Ni = mi * ixi;

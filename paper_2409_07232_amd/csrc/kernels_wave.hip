@@ -29,8 +29,9 @@
 //    second pass of the method itself, every pair scaled by the smallest
 //    sigma = M / D over the bins where the pair's net is negative.
 // FP64 mode: the method in FP64 with FP64 sums.  FP32C mode: normalised
-// masses, FP32 pair arithmetic, compensated FP32 sums (TwoSum error
-// capture), FP64 totals and FP64 update; a point at which the limiter fires
+// masses, FP32 pair arithmetic, the FP32 amounts summed per bin in FP64
+// (each enters its sums exactly, so a transfer leaves and enters with the
+// same value), FP64 totals and FP64 update; a point at which the limiter fires
 // takes that and every remaining step of the call in FP64 mode (a follow-up
 // launch over those points only), since emptying a bin by cancellation
 // needs FP64 to stay conservative and positive.
@@ -680,6 +681,8 @@ __global__ void __launch_bounds__(kWave)
   npairs = wave_sum_u64(npairs);
   if (threadIdx.x == 0) {
     if (npairs) atomicAdd(&a.counters[0], npairs);
+    // pairs of the FP64 follow-up of FP32C points, counted apart as well
+    if (npairs && a.pending_only) atomicAdd(&a.counters[4], npairs);
     if (nlim) atomicAdd(&a.counters[1], nlim);
     if (nfp64) atomicAdd(&a.counters[2], nfp64);
   }

@@ -123,7 +123,11 @@ __device__ __noinline__ int slow_step_core(const DevModel &m, double *st,
           if (Mt[a * B + i] == 0.0) continue;
           for (int j = (a == b ? i : 0); j < B; ++j) {
             if (Mt[b * B + j] == 0.0) continue;
-            if (pass == 0 && m.kt[i * B + j] >= 0) ++cnt;
+            // counted like the fast kernels: target on the grid and a
+            // kernel entry nonzero at some level (one species here)
+            if (pass == 0 && m.kt[i * B + j] >= 0 &&
+                ((m.nzT[j] >> i) & 1ull))
+              ++cnt;
             PairNets pn;
             const double K = kernel_at_f64(m, ab, br, i, j, w);
             if (!pair_nets_f64(m, Mt, Nv, a, i, b, j, K, dt, pn)) continue;

@@ -9,8 +9,8 @@ The paper benchmarks on the CONUS-12km WRF case (425 x 300 x 50 points,
 dt = 5 s; Sec. IV) whose data and FSBM kernel files are not available here.
 These generators stand in for them with the shapes of that workload: 33 mass
 doubling bins per particle type (Sec. III), kernel tables at several pressure
-levels interpolated per point (Sec. V-A), and a minority of cloudy points
-(Sec. VII discusses that many cells hold no cloud).
+levels interpolated per point (Sec. VI-A), and a minority of cloudy points
+(Sec. VIII discusses that many cells hold no cloud).
 
 Seeds: numpy PCG64(240907232 + config_id).
 """

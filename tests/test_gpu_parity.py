@@ -45,7 +45,7 @@ def test_golovin_full_run(precision):
     ref, x, lim = run_oracle(w.subset(np.arange(1)))
     got, st, _ = run_gpu(w, precision)
     check(got, np.repeat(ref, 64, axis=0), w.N, x, precision, "golovin",
-          limited=np.repeat(lim, 64))
+          limited=lim.repeat(64))
     assert st["active_points"] == 64
     assert st["limiter_steps"] == 0
 
@@ -160,13 +160,21 @@ def test_totals_and_pair_count(precision):
     assert np.allclose(ma, m1, rtol=1e-14, atol=0)
     assert np.allclose(nb, w.N.sum(axis=(1, 2)), rtol=1e-14, atol=0)
     assert np.all(na <= nb * (1 + 1e-12))
-    # pairs of one step: both bins active (M >= theta M_tot), target on grid
+    # pairs of one step: both bins active (M >= theta M_tot), target on
+    # the grid and a kernel entry nonzero at some level; the gravitational
+    # kernel is zero on the diagonal (equal fall speeds), so no self pair
     M = w.N[:, 0, :] * x
     tot = M.sum(axis=1, keepdims=True)
     act = (M > 0) & (M >= 1e-30 * tot)
+    B = w.nbins
+    i, j = np.triu_indices(B)
+    on_grid = (i != j) | (j < B - 1)      # (B-1, B-1) leaves the grid
+    nonzero = np.any(w.tables[0][:, i, j] != 0.0, axis=0)
+    assert not nonzero[i == j].any()
+    keep = on_grid & nonzero
+    want = int((act[:, i[keep]] & act[:, j[keep]]).sum())
     n = act.sum(axis=1)
-    top = act[:, -1]
-    want = int((n * (n + 1) // 2 - top).sum())
+    assert want == int((n * (n - 1) // 2).sum())
     assert st["pair_evals"] == want
 
 

@@ -96,7 +96,7 @@ def test_golovin_full_run():
     ref, x, lim = run_oracle(w.subset(np.arange(1)), order=1)
     got, st, _ = run_gpu(w)
     check(got, np.repeat(ref, 64, axis=0), w.N, x, 0, "seq-golovin",
-          limited=np.repeat(lim, 64))
+          limited=lim.repeat(64))
     assert st["active_points"] == 64
 
 

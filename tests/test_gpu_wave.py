@@ -127,6 +127,55 @@ def test_multi_grid_launch(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_multi_grid_graph_follows_workspace_changes(precision):
+    """A multi-grid call caches its hipGraph in the widest handle, and the
+    graph holds every grid's workspace pointers.  When another handle's
+    workspace is reallocated (a larger single-grid call on it) or that
+    handle is replaced by a new one, the next multi-grid call with the same
+    arguments captures a new graph instead of replaying the old one, and
+    its results equal the per-grid calls bit for bit."""
+    L = _lib()
+    ws = wl.config5(npoints=3000, nsteps=6)
+    hs = [L.FsbmCoal.from_workload(w, precision=precision) for w in ws]
+    widest = max(range(3), key=lambda g: ws[g].nspecies * ws[g].nbins)
+    others = [g for g in range(3) if g != widest]
+    s = torch.cuda.Stream()
+    Ns = [torch.from_numpy(np.array(w.N, copy=True)).to("cuda") for w in ws]
+    N0 = [n.clone() for n in Ns]
+    ps = [torch.from_numpy(np.array(w.p, copy=True)).to("cuda") for w in ws]
+    single = [gpu_run(w, precision, flags=L.FLAG_FORCE_WAVE)[0] for w in ws]
+
+    def multi():
+        with torch.cuda.stream(s):
+            for n, n0 in zip(Ns, N0):
+                n.copy_(n0)
+            L.step_multi(hs, Ns, ps, ws[0].dt, ws[0].nsteps, stream=s)
+        s.synchronize()
+        for g in range(3):
+            assert np.array_equal(Ns[g].cpu().numpy(), single[g]), g
+        return hs[widest].stats()["graph_captures"]
+
+    assert multi() == 1
+    assert multi() == 1          # same arguments and workspaces: replayed
+    # a larger call on another grid reallocates its workspace
+    g = others[0]
+    big = np.concatenate([ws[g].N] * 3)
+    Nb = torch.from_numpy(big).to("cuda")
+    pb = torch.from_numpy(np.concatenate([ws[g].p] * 3)).to("cuda")
+    hs[g].step(Nb, pb, ws[g].dt, 2, stream=s)
+    s.synchronize()
+    assert multi() == 2
+    assert multi() == 2
+    # a grid's handle replaced by a new one (possibly at the same address)
+    g = others[1]
+    hs[g].close()
+    hs[g] = L.FsbmCoal.from_workload(ws[g], precision=precision)
+    assert multi() == 3
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_autotune_keeps_results(precision, tmp_path, monkeypatch):
     L = _lib()
     monkeypatch.setenv("FSBM_TUNE_CACHE", str(tmp_path / "tune.txt"))
@@ -258,11 +307,14 @@ def test_full_size_four_species_sampled(precision, four_species_full):
     _full_size_sampled([four_species_full], precision, "full4", False)
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("precision", [1, 0])
-def test_full_size_refined_132_sampled(precision):
-    """Liquid + graupel on 132 bins at full size: 262,144 points, 100
-    steps of 2 s."""
-    _full_size_sampled([wl.config4(nbins=132)], precision, "full132", False)
+@pytest.mark.parametrize("nbins", [66, 132, 264])
+def test_full_size_refined_sampled(nbins, precision):
+    """Liquid + graupel on the refined grids (mass ratio 2^(1/2), 2^(1/4),
+    2^(1/8)) at full size: 262,144 points, 100 steps of 2 s each."""
+    _full_size_sampled([wl.config4(nbins=nbins)], precision,
+                       "full%d" % nbins, False)
 
 
 @pytest.fixture(scope="module")
