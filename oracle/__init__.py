@@ -22,17 +22,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fsbm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
           "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
+# With FSBM_ORACLE_SANITIZE=1 the oracle is built and loaded with the
+# address and undefined-behaviour checkers (a CPU build; the Python process
+# must preload the address checker's runtime, see tests/test_oracle_asan.py)
+SANITIZE = os.environ.get("FSBM_ORACLE_SANITIZE", "") == "1"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
+_LIB = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else
+                    "liboracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` with gcc."""
+    """Compile the oracle into ``oracle/liboracle.so`` with gcc (or the
+    checked build ``liboracle_san.so``)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"]
+        cmd = ["gcc", *CFLAGS, *(SAN_FLAGS if SANITIZE else []), _SRC, "-o",
+               tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -71,6 +80,11 @@ def _load():
                                         ip, ctypes.POINTER(ctypes.c_uint8),
                                         ctypes.c_int32]
         lib.fsbm_oracle_run.restype = ctypes.c_int
+        lib.fsbm_oracle_run_gated.argtypes = [
+            ctypes.POINTER(_Desc), dp, dp, dp, dp, ctypes.c_int64,
+            ctypes.c_double, ctypes.c_int32, dp, dp, dp, dp, lp, ip,
+            ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32]
+        lib.fsbm_oracle_run_gated.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
         lib.fsbm_oracle_targets.argtypes = [ctypes.POINTER(_Desc), ip, dp]
@@ -139,8 +153,10 @@ class OracleModel:
                                              float(p), a, b, i, j)
 
     def run(self, N: np.ndarray, p: np.ndarray, dt: float, nsteps: int,
-            nthreads: int = 0, totals: bool = False):
-        """Advance ``N`` ([P][S][B] float64, modified in place)."""
+            nthreads: int = 0, totals: bool = False, t_old=None, t_now=None):
+        """Advance ``N`` ([P][S][B] float64, modified in place).  With
+        t_old / t_now ([P] temperatures in K), only the points with
+        t_old > 193.15 and t_now > 223.15 take part."""
         if N.dtype != np.float64 or not N.flags.c_contiguous:
             raise ValueError("N must be C-contiguous float64")
         P = int(N.shape[0])
@@ -153,8 +169,17 @@ class OracleModel:
         lim = ctypes.c_int64(0)
         lim_pt = np.zeros(P, dtype=np.int32)
         lim_bins = np.zeros(N.shape, dtype=np.uint8)
-        rc = _load().fsbm_oracle_run(
-            ctypes.byref(self._desc), _dptr(N), _dptr(p), P, float(dt),
+        temps = []
+        for t in (t_old, t_now):
+            if t is not None:
+                t = np.ascontiguousarray(t, dtype=np.float64)
+                if t.shape != (P,):
+                    raise ValueError("temperatures must be [npoints]")
+            temps.append(t)
+        rc = _load().fsbm_oracle_run_gated(
+            ctypes.byref(self._desc), _dptr(N), _dptr(p),
+            *[(_dptr(t) if t is not None else None) for t in temps], P,
+            float(dt),
             int(nsteps), *[(_dptr(o) if o is not None else None)
                            for o in outs], ctypes.byref(lim),
             lim_pt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

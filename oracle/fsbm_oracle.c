@@ -492,12 +492,41 @@ int fsbm_oracle_max_threads(void) {
 #endif
 }
 
+/* The collision call of a point is made only where the point is warm
+   enough: the main loop over grid points (Sec. III, its listing) calls the
+   collision routine inside a test of the previous temperature against
+   193.15 K and, nested in it, of the current one against 223.15 K, both
+   strict.  A missing array (NULL) passes its test. */
+#define T_OLD_MIN 193.15
+#define T_COLL_MIN 223.15
+
+static int point_passes_gate(const double *t_old, const double *t_now,
+                             int64_t pt) {
+  if (t_old && !(t_old[pt] > T_OLD_MIN)) return 0;
+  if (t_now && !(t_now[pt] > T_COLL_MIN)) return 0;
+  return 1;
+}
+
 int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t npoints, double dt, int32_t nsteps,
                     double *mass_before, double *mass_after,
                     double *num_before, double *num_after,
                     int64_t *limiter_steps, int32_t *limiter_per_point,
                     unsigned char *limited_bins, int32_t nthreads) {
+  return fsbm_oracle_run_gated(d, N, p, NULL, NULL, npoints, dt, nsteps,
+                               mass_before, mass_after, num_before,
+                               num_after, limiter_steps, limiter_per_point,
+                               limited_bins, nthreads);
+}
+
+int fsbm_oracle_run_gated(const fsbm_oracle_desc *d, double *N,
+                          const double *p, const double *t_old,
+                          const double *t_now, int64_t npoints, double dt,
+                          int32_t nsteps, double *mass_before,
+                          double *mass_after, double *num_before,
+                          double *num_after, int64_t *limiter_steps,
+                          int32_t *limiter_per_point,
+                          unsigned char *limited_bins, int32_t nthreads) {
   if (check_desc(d) || npoints < 0 || nsteps < 0 || !(dt > 0.0) ||
       !isfinite(dt))
     return -1;
@@ -552,7 +581,8 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
         int32_t lim_pt = 0;
         unsigned char *lb = limited_bins ? limited_bins + pt * n : NULL;
         if (lb) memset(lb, 0, (size_t)n);
-        for (int st = 0; st < nsteps; ++st)
+        const int steps = point_passes_gate(t_old, t_now, pt) ? nsteps : 0;
+        for (int st = 0; st < steps; ++st)
           lim_pt += d->order == 1
                         ? step_point_seq(&cx, Np, p[pt], dt, wk.M, lb)
                         : step_point(&cx, Np, p[pt], dt, &wk, lb);

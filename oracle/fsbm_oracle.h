@@ -66,6 +66,19 @@ int fsbm_oracle_run(const fsbm_oracle_desc *d, double *N, const double *p,
                     int64_t *limiter_steps, int32_t *limiter_per_point,
                     unsigned char *limited_bins, int32_t nthreads);
 
+/* The same, for the points whose collision call the main loop makes
+ * (Sec. III listing): a point is advanced only if t_old[pt] > 193.15 K and
+ * t_now[pt] > 223.15 K (K; either array NULL = that test passes); the
+ * other points are left unchanged. */
+int fsbm_oracle_run_gated(const fsbm_oracle_desc *d, double *N,
+                          const double *p, const double *t_old,
+                          const double *t_now, int64_t npoints, double dt,
+                          int32_t nsteps, double *mass_before,
+                          double *mass_after, double *num_before,
+                          double *num_after, int64_t *limiter_steps,
+                          int32_t *limiter_per_point,
+                          unsigned char *limited_bins, int32_t nthreads);
+
 /* Bin masses x_k, k = 0..B-1. */
 int fsbm_oracle_grid(const fsbm_oracle_desc *d, double *x);
 

@@ -273,6 +273,65 @@ def config3(npoints: int = 1 << 20, nsteps: int = 100,
                     meta={"species": SPECIES_4})
 
 
+# ------------------------------------------------- ice-crystal habits
+# FSBM keeps the ice-crystal spectrum per habit (a second dimension of the
+# crystal arrays, Sec. VI-C); here three habits (columns, plates,
+# dendrites) are three species beside liquid, snow, graupel and hail.
+SPECIES_7 = ("liquid", "ice_columns", "ice_plates", "ice_dendrites", "snow",
+             "graupel", "hail")
+BETA_7 = (0.8, 0.3, 0.25, 0.2, 0.4, 0.6, 0.7)
+RHO_7 = (1.0, 0.9, 0.9, 0.5, 0.1, 0.4, 0.9)
+RBAR_7 = (10.0e-4, 100.0e-4, 100.0e-4, 150.0e-4, 300.0e-4, 500.0e-4,
+          800.0e-4)
+CONTENT_7 = ((0.1, 3.0), (0.01, 0.1), (0.01, 0.1), (0.01, 0.1), (0.01, 0.5),
+             (0.01, 1.0), (0.01, 0.5))
+PRESENCE_7 = (1.0, 0.3, 0.3, 0.3, 0.3, 0.3, 0.1)
+
+
+def _product_7():
+    """Product species of the seven-species set (symmetric): drops rimed
+    onto a particle keep its species (l + x -> x), two crystals of any
+    habits and crystals with snow aggregate to snow, anything with graupel
+    is graupel, anything with hail is hail."""
+    S = 7
+    P = np.zeros((S, S), dtype=np.int32)
+    for a in range(S):
+        for b in range(a, S):
+            if a == 0:
+                q = b
+            elif b == 6:
+                q = 6
+            elif b == 5:
+                q = 5
+            else:
+                q = 4          # habits and snow among themselves
+            P[a, b] = P[b, a] = q
+    return P
+
+
+PRODUCT_7 = _product_7()
+
+
+def config_habits(npoints: int = 1 << 18, nsteps: int = 100,
+                  dt: float = 2.0) -> Workload:
+    """Seven species: liquid, three ice-crystal habits, snow, graupel and
+    hail on 33 doubling bins, 28 pair kernels; random presence per species
+    and uneven active windows as in the four-species workload."""
+    rng = rng_for(6)
+    B, S = 33, 7
+    x = bin_masses(B)
+    present = rng.random((npoints, S)) < np.array(PRESENCE_7)[None, :]
+    present[:, 0] = True
+    N = _multi_species_states(rng, x, RHO_7, RBAR_7, CONTENT_7, present,
+                              npoints, ((0, 5), (15, 32)))
+    p = rng.uniform(500.0, 1000.0, npoints)
+    tables = gravitational_tables(B, 1, RHO_7, BETA_7,
+                                  multi_species_vcoef(BETA_7), P_LEVELS_3)
+    return Workload("seven_species_habits", B, S, 1, tables,
+                    P_LEVELS_3.copy(), PRODUCT_7.copy(), N, p, dt, nsteps,
+                    meta={"species": SPECIES_7})
+
+
 # ---------------------------------------------------------------- config 4
 def _liquid_graupel():
     """Densities, exponents, mean radii and content ranges of the two
@@ -336,6 +395,18 @@ def config5(npoints: int = 1 << 22, nsteps: int = 100, dt: float = 2.0,
                             P_LEVELS_3.copy(), prod.copy(), N, p, dt, nsteps,
                             meta={"global_index": sel}))
     return out
+
+
+def temperatures(npoints: int, seed: int = 0, lo: float = 185.0,
+                 hi: float = 300.0):
+    """Seeded per-point temperatures (K) for the collision gate: the
+    current temperature uniform in [lo, hi] and the previous one within a
+    few kelvin of it, so that points fall on both sides of both gate
+    thresholds (193.15 K and 223.15 K).  Returns (t_old, t_now)."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 2000 + seed))
+    t_now = rng.uniform(lo, hi, npoints)
+    t_old = t_now + rng.normal(0.0, 3.0, npoints)
+    return t_old, t_now
 
 
 def sample_active(w: Workload, n: int, seed: int = 0) -> np.ndarray:

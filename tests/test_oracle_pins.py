@@ -279,6 +279,20 @@ def test_laws_four_species_subset():
     _check_laws(wl.config3(npoints=512), 8, 20)
 
 
+def test_laws_seven_species_habits_subset():
+    _check_laws(wl.config_habits(npoints=512), 8, 20)
+
+
+def test_habit_product_map_is_symmetric_and_closed():
+    P = wl.PRODUCT_7
+    assert np.array_equal(P, P.T)
+    assert P.min() >= 0 and P.max() < 7
+    # drops keep the collector's species; a collision never yields liquid
+    # unless both partners are liquid
+    assert P[0].tolist() == list(range(7))
+    assert (P[1:, 1:] > 0).all()
+
+
 def test_laws_refined_two_species_subset():
     _check_laws(wl.config4(nbins=66, npoints=64), 3, 10)
 
@@ -454,3 +468,36 @@ def test_tiny_cases_against_50_digit_transcription(seed):
                      lev.tolist(), prod.tolist())
     Nref = np.array([[[float(v) for v in Nm[a]] for a in range(S)]])
     assert compare.rel_bin(Nc, Nref, x) < 1e-13
+
+
+def test_collision_temperature_gate():
+    """The main loop calls the collision routine only where the previous
+    temperature exceeds 193.15 K and the current one 223.15 K, both strict
+    (Sec. III listing): gated points are left bitwise unchanged, the others
+    step exactly as without the gate, and a point exactly at a threshold is
+    gated."""
+    w = wl.config2(nx=8, ny=8, nz=50)
+    cl = np.flatnonzero(w.cloudy())[:400]
+    sub = w.subset(cl)
+    P = sub.npoints
+    t_old, t_now = wl.temperatures(P, seed=1)
+    # thresholds themselves, and the next double above them
+    t_now[:4] = [223.15, np.nextafter(223.15, np.inf), 250.0, 250.0]
+    t_old[:4] = [250.0, 250.0, 193.15, np.nextafter(193.15, np.inf)]
+    om = oracle.OracleModel(sub.nbins, 1, sub.tables, sub.p_levels,
+                            sub.product)
+    gated = sub.N.copy()
+    om.run(gated, sub.p, sub.dt, 20, t_old=t_old, t_now=t_now)
+    free = sub.N.copy()
+    om.run(free, sub.p, sub.dt, 20)
+    on = (t_old > 193.15) & (t_now > 223.15)
+    assert on.tolist()[:4] == [False, True, False, True]
+    assert 0 < on.sum() < P
+    assert np.array_equal(gated[~on], sub.N[~on])
+    assert np.array_equal(gated[on], free[on])
+    assert not np.array_equal(free[~on], sub.N[~on])
+    # every point warm: the gate changes nothing
+    warm = sub.N.copy()
+    om.run(warm, sub.p, sub.dt, 20, t_old=np.full(P, 280.0),
+           t_now=np.full(P, 280.0))
+    assert np.array_equal(warm, free)
