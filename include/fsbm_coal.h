@@ -135,6 +135,27 @@ int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
                    void *stream);
 
 /*
+ * fsbm_coal_step with the temperature gates of FSBM's loop over grid points
+ * (Sec. III, main-loop listing): a point's microphysics runs only where its
+ * previous temperature exceeds 193.15 K, and the collision routine within it
+ * only where the current temperature exceeds 223.15 K.  A point takes part
+ * in the call iff it holds mass, t_old_k[pt] > 193.15 and
+ * t_now_k[pt] > 223.15 (strict; a NaN temperature fails); every other point
+ * is left unchanged bit for bit, and fsbm_coal_totals reports its mass and
+ * number as both before and after.
+ *  t_old_k  device, FP64, [npoints] previous temperature (K), or NULL (that
+ *           test passes for every point)
+ *  t_now_k  device, FP64, [npoints] current temperature (K), or NULL
+ * Other arguments, ownership, errors and results (for the points that pass)
+ * as fsbm_coal_step, which is this call with both arrays NULL.  The
+ * temperatures are read on the device when the call runs, like N.
+ */
+int fsbm_coal_step_gated(fsbm_coal_t h, double *N, const double *p_hpa,
+                         const double *t_old_k, const double *t_now_k,
+                         int64_t npoints, double dt_s, int32_t nsteps,
+                         void *stream);
+
+/*
  * One launch sequence over several handles with different grids (mixed
  * 33/66/132-bin batches): the cloudy points of every grid are compacted into
  * one work list and advanced by one persistent kernel per group of fused

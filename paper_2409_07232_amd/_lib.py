@@ -34,6 +34,7 @@ FLAG_PROFILE = 8
 
 # every entry point declared in include/fsbm_coal.h
 EXPORTS = ("fsbm_coal_opts_default", "fsbm_coal_create", "fsbm_coal_step",
+           "fsbm_coal_step_gated",
            "fsbm_coal_step_multi", "fsbm_coal_tune", "fsbm_coal_totals",
            "fsbm_coal_get_stats", "fsbm_coal_destroy", "fsbm_coal_strerror",
            "fsbm_coal_last_error")
@@ -98,6 +99,9 @@ def load(path: str = LIB_PATH):
     lib.fsbm_coal_step.argtypes = [vp, vp, vp, ctypes.c_int64,
                                    ctypes.c_double, ctypes.c_int32, vp]
     lib.fsbm_coal_step.restype = ctypes.c_int
+    lib.fsbm_coal_step_gated.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64,
+                                         ctypes.c_double, ctypes.c_int32, vp]
+    lib.fsbm_coal_step_gated.restype = ctypes.c_int
     lib.fsbm_coal_step_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                          ctypes.POINTER(vp),
                                          ctypes.POINTER(vp),
@@ -213,6 +217,27 @@ class FsbmCoal:
                                    _stream_handle(stream))
         if rc != FSBM_OK:
             self._raise(rc, "fsbm_coal_step")
+        self._last_npoints = P
+
+    def step_gated(self, N, p, t_old, t_now, dt: float, nsteps: int,
+                   stream=None):
+        """step() with the temperature gates (``fsbm_coal_step_gated``):
+        t_old / t_now are [P] float64 device tensors (K) or None."""
+        _check_state(N, self.nspecies, self.nbins)
+        P = int(N.shape[0])
+        _check_p(p, P)
+        ptrs = []
+        for t in (t_old, t_now):
+            if t is None:
+                ptrs.append(None)
+            else:
+                _check_p(t, P)
+                ptrs.append(t.data_ptr())
+        rc = load().fsbm_coal_step_gated(self._h, N.data_ptr(), p.data_ptr(),
+                                         ptrs[0], ptrs[1], P, float(dt),
+                                         int(nsteps), _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_step_gated")
         self._last_npoints = P
 
     def totals(self):

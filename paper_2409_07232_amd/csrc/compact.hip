@@ -3,9 +3,10 @@
 //
 // The paper isolates the collision call behind a per-point predicate array
 // (Sec. VI-B) and notes that cloud-free cells need far less work (Sec. VIII).
-// Here a point is cloudy iff it holds mass; collisions neither create nor
-// remove a point's mass, so the cloudy set is fixed for the whole call and
-// is built once per call:
+// Here a point is cloudy iff it holds mass (and, with temperatures given,
+// passes the gates of FSBM's main loop, Sec. III); collisions neither create
+// nor remove a point's mass, so the cloudy set is fixed for the whole call
+// and is built once per call:
 //   count   per block of points: a cloudy flag per point (the block's rows
 //           read with coalesced loads) and cloudy points per pressure
 //           bracket
@@ -35,6 +36,13 @@ namespace {
 
 constexpr int kCompactThreads = 256;
 
+// Temperature gates of FSBM's loop over grid points (Sec. III, main-loop
+// listing): the microphysics of a point runs only where its previous
+// temperature exceeds 193.15 K, and collisions within it only where the
+// current temperature exceeds 223.15 K; both comparisons strict.
+constexpr double kTOldMin = 193.15;
+constexpr double kTCollMin = 223.15;
+
 // Pressure bracket and weight of level l: clamp p into the tabulated range,
 // take the first level pair with p_l >= p >= p_{l+1}, w is the weight of
 // level l (linear interpolation, Sec. VI-A).
@@ -52,7 +60,11 @@ __device__ __forceinline__ void bracket_of(const double *plev, int L,
   w = (p - plev[b + 1]) / (plev[b] - plev[b + 1]);
 }
 
-// Cloudy flags and per-bracket counts of one block of points.  The block's
+// Cloudy flags and per-bracket counts of one block of points.  Flag 1: the
+// point holds mass and passes the temperature gates (t_old, t_now; a null
+// array passes its test), so it takes part in the call; flag 2: it holds
+// mass but a gate stops it (left unchanged, totals still recorded); flag 0:
+// no mass.  The block's
 // rows are one contiguous run of S*B doubles per point: its threads read
 // the run with consecutive addresses (one wave load covers 512 bytes) and
 // mark the point of every positive entry in LDS; the point of entry e is
@@ -63,7 +75,9 @@ __global__ void __launch_bounds__(kCompactThreads)
                   int64_t npoints, int SB, unsigned magic,
                   const double *__restrict__ plev, int L,
                   int *__restrict__ block_counts,
-                  unsigned char *__restrict__ cloudy) {
+                  unsigned char *__restrict__ cloudy,
+                  const double *__restrict__ t_old,
+                  const double *__restrict__ t_now) {
   __shared__ int cnt[kMaxBuckets];
   __shared__ unsigned char wet[kCompactThreads];
   const int t = threadIdx.x;
@@ -93,8 +107,12 @@ __global__ void __launch_bounds__(kCompactThreads)
   }
   __syncthreads();
   if (t < np) {
-    const bool c = wet[t] != 0;
-    cloudy[p0 + t] = c ? 1 : 0;
+    const bool has_mass = wet[t] != 0;
+    bool c = has_mass;
+    // a NaN temperature fails its test
+    if (c && t_old) c = t_old[p0 + t] > kTOldMin;
+    if (c && t_now) c = t_now[p0 + t] > kTCollMin;
+    cloudy[p0 + t] = c ? 1 : (has_mass ? 2 : 0);
     if (c) {
       int l;
       double w;
@@ -173,7 +191,9 @@ __global__ void __launch_bounds__(kCompactThreads)
   const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
   const bool inside = pt < npoints;
   const double *row = N + (inside ? pt : 0) * SB;
-  const bool cloudy = inside && cloudy_flag[pt] != 0;
+  const bool cloudy = inside && cloudy_flag[pt] == 1;
+  // gated points keep their mass: their totals are still recorded
+  const bool has_mass = inside && cloudy_flag[pt] != 0;
   int l = 0;
   double w = 0.0;
   if (cloudy) bracket_of(plev, L, p[pt], l, w);
@@ -188,7 +208,7 @@ __global__ void __launch_bounds__(kCompactThreads)
   __syncthreads();
   // FP64 totals of the point (one pass over its row)
   double m = 0.0, n = 0.0;
-  if (cloudy)
+  if (has_mass)
     for (int a = 0; a < S; ++a)
       for (int k = 0; k < B; ++k) {
         const double v = row[a * B + k];
@@ -227,7 +247,7 @@ __global__ void __launch_bounds__(kCompactThreads)
   }
   if (inside && tot) {
     tot[pt] = m;                     // mass before
-    tot[(size_t)npoints + pt] = m;   // mass after (cloud-free: unchanged)
+    tot[(size_t)npoints + pt] = m;   // mass after (if not stepped: unchanged)
     tot[2 * (size_t)npoints + pt] = n;
     tot[3 * (size_t)npoints + pt] = n;
   }
@@ -431,6 +451,7 @@ hipError_t launch_compact_count(const double *N, const double *p,
                                 int64_t npoints, int SB, const double *plev,
                                 int L, int *block_counts,
                                 unsigned char *cloudy, int nblocks,
+                                const double *t_old, const double *t_now,
                                 hipStream_t st) {
   if (SB < 1 || SB > kWave * kMaxOwn ||
       npoints > (int64_t)nblocks * kCompactThreads)
@@ -438,7 +459,7 @@ hipError_t launch_compact_count(const double *N, const double *p,
   const unsigned magic = 0xffffffffu / (unsigned)SB + 1u;
   hipLaunchKernelGGL(compact_count, dim3(nblocks), dim3(kCompactThreads), 0,
                      st, N, p, npoints, SB, magic, plev, L, block_counts,
-                     cloudy);
+                     cloudy, t_old, t_now);
   return hipGetLastError();
 }
 

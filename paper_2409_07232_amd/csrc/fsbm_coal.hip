@@ -45,7 +45,7 @@ std::atomic<uint64_t> g_generation{0};
 
 // Arguments a captured graph depends on.
 struct GraphKey {
-  std::vector<const void *> ptrs;  // N and p of every grid
+  std::vector<const void *> ptrs;  // N, p, t_old, t_now of every grid
   std::vector<int64_t> npts;
   std::vector<const void *> handles;
   std::vector<uint64_t> gens;      // generation of every grid's handle
@@ -80,7 +80,6 @@ struct fsbm_coal_s {
   void *wmem = nullptr;
   int64_t wpoints = -1;  // points the workspace was laid out for
   DevWork ws{};
-  int nblocks = 0;
   // graph cache
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -528,37 +527,71 @@ void drop_graph(fsbm_coal_t h) {
   h->gkey = GraphKey();
 }
 
-// Workspace for up to npoints points: slots, state (two buffers for the
-// lane kernels), weights, compaction scratch, totals, counters, pending-step
-// counters and sort keys, in one allocation.
-int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
-  if (npoints <= h->wpoints) return FSBM_OK;
+// Workspace of a call over up to npoints points: slots, state (two buffers
+// for the lane kernels), weights, compaction scratch, totals, counters,
+// pending-step counters, sort keys and cloudy flags, in one block.  The
+// layout depends on the handle's shape and npoints only.
+struct WsLayout {
+  int cap = 0, nblocks = 0;
+  size_t o_state = 0, o_state2 = 0, o_wgt = 0, o_tot = 0, o_slot = 0,
+         o_bc = 0, o_bo = 0, o_meta = 0, o_cnt = 0, o_pend = 0, o_keys = 0,
+         o_wet = 0, bytes = 0;
+};
+
+int ws_layout(fsbm_coal_t h, int64_t npoints, WsLayout &L) {
   const int SB = h->S * h->B;
   const int64_t cap64 = (int64_t)align_up(
       (size_t)npoints + (size_t)kWave * h->dm.nbr, kSlotAlign);
   if (cap64 > (int64_t)0x7fffff00) return FSBM_EUNSUPPORTED;
-  const int cap = (int)cap64;
-  const int nblocks = (int)((npoints + kCompactBlock - 1) / kCompactBlock);
+  L.cap = (int)cap64;
+  L.nblocks = (int)((npoints + kCompactBlock - 1) / kCompactBlock);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align_up(off + bytes, 256);
     return o;
   };
-  const size_t o_state = take(sizeof(double) * (size_t)SB * cap);
+  L.o_state = take(sizeof(double) * (size_t)SB * L.cap);
   // the lane kernels read a step's state from one buffer and write the other
-  const size_t o_state2 =
-      h->lane ? take(sizeof(double) * (size_t)SB * cap) : 0;
-  const size_t o_wgt = take(sizeof(double) * cap);
-  const size_t o_tot = take(sizeof(double) * 4 * (size_t)npoints);
-  const size_t o_slot = take(sizeof(int) * cap);
-  const size_t o_bc = take(sizeof(int) * (size_t)nblocks * kMaxBuckets);
-  const size_t o_bo = take(sizeof(int) * (size_t)nblocks * kMaxBuckets);
-  const size_t o_meta = take(sizeof(CompactMeta));
-  const size_t o_cnt = take(sizeof(unsigned long long) * kNumCounters);
-  const size_t o_pend = take(sizeof(int) * cap);
-  const size_t o_keys = h->lane ? take(sizeof(unsigned) * cap) : 0;
-  const size_t o_wet = take((size_t)npoints);
+  L.o_state2 = h->lane ? take(sizeof(double) * (size_t)SB * L.cap) : 0;
+  L.o_wgt = take(sizeof(double) * L.cap);
+  L.o_tot = take(sizeof(double) * 4 * (size_t)npoints);
+  L.o_slot = take(sizeof(int) * L.cap);
+  L.o_bc = take(sizeof(int) * (size_t)L.nblocks * kMaxBuckets);
+  L.o_bo = take(sizeof(int) * (size_t)L.nblocks * kMaxBuckets);
+  L.o_meta = take(sizeof(CompactMeta));
+  L.o_cnt = take(sizeof(unsigned long long) * kNumCounters);
+  L.o_pend = take(sizeof(int) * L.cap);
+  L.o_keys = h->lane ? take(sizeof(unsigned) * L.cap) : 0;
+  L.o_wet = take((size_t)npoints);
+  L.bytes = off;
+  return FSBM_OK;
+}
+
+void ws_bind(fsbm_coal_t h, const WsLayout &L, unsigned char *b,
+             int64_t npoints, DevWork &w) {
+  w.npoints = npoints;
+  w.slot_cap = L.cap;
+  w.nblocks = L.nblocks;
+  w.state = (double *)(b + L.o_state);
+  w.state_alt = h->lane ? (double *)(b + L.o_state2) : nullptr;
+  w.wgt = (double *)(b + L.o_wgt);
+  w.tot = (double *)(b + L.o_tot);
+  w.slot_point = (int *)(b + L.o_slot);
+  w.block_counts = (int *)(b + L.o_bc);
+  w.block_offsets = (int *)(b + L.o_bo);
+  w.meta = (CompactMeta *)(b + L.o_meta);
+  w.counters = (unsigned long long *)(b + L.o_cnt);
+  w.pending = (int *)(b + L.o_pend);
+  w.keys = h->lane ? (unsigned *)(b + L.o_keys) : nullptr;
+  w.cloudy = b + L.o_wet;
+}
+
+// The handle's own workspace, grown to npoints points (hipMalloc).
+int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
+  if (npoints <= h->wpoints) return FSBM_OK;
+  WsLayout L;
+  RC_TRY(ws_layout(h, npoints, L));
   drop_graph(h);
   if (h->wmem) hipFree(h->wmem);
   h->wmem = nullptr;
@@ -566,33 +599,18 @@ int ensure_workspace(fsbm_coal_t h, int64_t npoints) {
   // every graph holding the old workspace (this handle's or another
   // handle's multi-grid graph) is stale from here on
   h->gen = ++g_generation;
-  hipError_t e = hipMalloc(&h->wmem, off);
+  hipError_t e = hipMalloc(&h->wmem, L.bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->last_error = "workspace allocation failed";
     return FSBM_ENOMEM;
   }
-  unsigned char *b = (unsigned char *)h->wmem;
-  h->ws.npoints = npoints;
-  h->ws.slot_cap = cap;
-  h->ws.state = (double *)(b + o_state);
-  h->ws.state_alt = h->lane ? (double *)(b + o_state2) : nullptr;
-  h->ws.wgt = (double *)(b + o_wgt);
-  h->ws.tot = (double *)(b + o_tot);
-  h->ws.slot_point = (int *)(b + o_slot);
-  h->ws.block_counts = (int *)(b + o_bc);
-  h->ws.block_offsets = (int *)(b + o_bo);
-  h->ws.meta = (CompactMeta *)(b + o_meta);
-  h->ws.counters = (unsigned long long *)(b + o_cnt);
-  h->ws.pending = (int *)(b + o_pend);
-  h->ws.keys = h->lane ? (unsigned *)(b + o_keys) : nullptr;
-  h->ws.cloudy = b + o_wet;
+  ws_bind(h, L, (unsigned char *)h->wmem, npoints, h->ws);
   // pending[] is kept at zero by the kernels after this first clear
-  e = hipMemset(h->ws.pending, 0, sizeof(int) * cap);
+  e = hipMemset(h->ws.pending, 0, sizeof(int) * L.cap);
   if (e != hipSuccess) return hip_fail(h, e, "hipMemset");
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
-  h->nblocks = nblocks;
   h->wpoints = npoints;
   return FSBM_OK;
 }
@@ -641,27 +659,33 @@ struct Call {
   std::vector<fsbm_coal_t> hs;
   std::vector<double *> N;
   std::vector<const double *> p;
+  // temperature gates (fsbm_coal_step_gated), null = no gate
+  std::vector<const double *> t_old, t_now;
   std::vector<int64_t> npts;
   double dt = 0.0;
   int nsteps = 0;
+  // workspace of every grid
+  std::vector<const DevWork *> ws;
   bool wave = false;  // one-point-per-wave kernel for every grid
   int spl = 0, wpb = 0, blocks = 0;
 };
 
-int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
-                     int64_t npoints, bool aos, hipStream_t st) {
+int enqueue_prologue(fsbm_coal_t h, const DevWork &w, double *N,
+                     const double *p, const double *t_old,
+                     const double *t_now, int64_t npoints, bool aos,
+                     hipStream_t st) {
   const DevModel &m = h->dm;
-  DevWork &w = h->ws;
   HIP_TRY(h, launch_zero_u64(w.counters, kNumCounters, st));
   HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
-                                  w.block_counts, w.cloudy, h->nblocks, st));
-  HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, h->nblocks,
+                                  w.block_counts, w.cloudy, w.nblocks,
+                                  t_old, t_now, st));
+  HIP_TRY(h, launch_compact_scan(w.block_counts, w.block_offsets, w.nblocks,
                                  m.nbr, w.meta, st));
   // one point per lane: slots are ordered by top active bin and mass
   // within chunks before the state is loaded (see compact.hip)
   unsigned *keys = aos ? nullptr : w.keys;
   HIP_TRY(h, launch_compact_gather(N, p, npoints, m.S, m.B, m.plev, m.L,
-                                   w.block_offsets, w.meta, h->nblocks,
+                                   w.block_offsets, w.meta, w.nblocks,
                                    w.slot_point, w.state, w.wgt, w.slot_cap,
                                    m.x, w.tot, aos ? 1 : 0, keys, m.theta,
                                    w.cloudy, st));
@@ -675,12 +699,16 @@ int enqueue_prologue(fsbm_coal_t h, double *N, const double *p,
 int enqueue_call(const Call &c, hipStream_t st) {
   fsbm_coal_t h0 = c.hs[0];
   for (size_t g = 0; g < c.hs.size(); ++g)
-    RC_TRY(enqueue_prologue(c.hs[g], c.N[g], c.p[g], c.npts[g], c.wave, st));
+    RC_TRY(enqueue_prologue(c.hs[g], *c.ws[g], c.N[g], c.p[g],
+                            g < c.t_old.size() ? c.t_old[g] : nullptr,
+                            g < c.t_now.size() ? c.t_now[g] : nullptr,
+                            c.npts[g], c.wave, st));
   const bool prof = (h0->flags & FSBM_FLAG_PROFILE) != 0;
+  const DevWork &w0 = *c.ws[0];
   StepArgs la{};
   WaveArgs wa{};
   if (!c.wave) {
-    const DevWork &w = h0->ws;
+    const DevWork &w = w0;
     la.m = h0->dm;
     la.slot_cap = w.slot_cap;
     la.slot_point = w.slot_point;
@@ -693,23 +721,23 @@ int enqueue_call(const Call &c, hipStream_t st) {
   } else {
     wa.ngrids = (int)c.hs.size();
     for (size_t g = 0; g < c.hs.size(); ++g) {
-      fsbm_coal_t h = c.hs[g];
+      const DevWork &w = *c.ws[g];
       WaveGrid &G = wa.g[g];
-      G.m = h->dm;
-      G.slot_point = h->ws.slot_point;
-      G.state = h->ws.state;
-      G.wgt = h->ws.wgt;
-      G.meta = h->ws.meta;
-      G.pending = h->ws.pending;
-      G.slot_cap = h->ws.slot_cap;
+      G.m = c.hs[g]->dm;
+      G.slot_point = w.slot_point;
+      G.state = w.state;
+      G.wgt = w.wgt;
+      G.meta = w.meta;
+      G.pending = w.pending;
+      G.slot_cap = w.slot_cap;
     }
     // counters of a multi-grid call are kept in the first handle
-    wa.counters = h0->ws.counters;
+    wa.counters = w0.counters;
     wa.dt = c.dt;
   }
   // lane kernels: a launch of n steps leaves the state in the buffer it
   // started from when n is even, in the other one when n is odd
-  double *lane_cur = h0->ws.state, *lane_alt = h0->ws.state_alt;
+  double *lane_cur = w0.state, *lane_alt = w0.state_alt;
   for (int done = 0; done < c.nsteps; done += c.spl) {
     const int n = std::min(c.spl, c.nsteps - done);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -723,14 +751,14 @@ int enqueue_call(const Call &c, hipStream_t st) {
       la.steps_left = c.nsteps - done;
       la.state = lane_cur;
       la.state_alt = lane_alt;
-      HIP_TRY(h0, launch_lane_seq(la, c.wpb, h0->ws.slot_cap, st));
+      HIP_TRY(h0, launch_lane_seq(la, c.wpb, w0.slot_cap, st));
     } else if (!c.wave) {
       la.nsteps = n;
       la.steps_left = c.nsteps - done;
       la.state = lane_cur;
       la.state_alt = lane_alt;
       HIP_TRY(h0, launch_lane_step(la, h0->precision, c.wpb,
-                                   h0->ws.slot_cap, st));
+                                   w0.slot_cap, st));
       if (n & 1) std::swap(lane_cur, lane_alt);
     } else {
       wa.nsteps = n;
@@ -748,7 +776,7 @@ int enqueue_call(const Call &c, hipStream_t st) {
   } else if (c.nsteps > 0 && !c.wave) {
     la.state = lane_cur;
     la.state_alt = lane_alt;
-    HIP_TRY(h0, launch_slow_steps(la, h0->ws.slot_cap, st));
+    HIP_TRY(h0, launch_slow_steps(la, w0.slot_cap, st));
   } else if (c.nsteps > 0 && h0->precision == FSBM_FP32C) {
     wa.pending_only = 1;
     HIP_TRY(h0, launch_wave_step(wa, h0->precision, c.blocks, st));
@@ -756,10 +784,11 @@ int enqueue_call(const Call &c, hipStream_t st) {
   for (size_t g = 0; g < c.hs.size(); ++g) {
     fsbm_coal_t h = c.hs[g];
     const DevModel &m = h->dm;
-    double *final_state = c.wave ? h->ws.state : lane_cur;
-    HIP_TRY(h, launch_scatter(c.N[g], c.npts[g], m.S, m.B, h->ws.meta,
-                              h->ws.slot_point, final_state, h->ws.slot_cap,
-                              m.x, h->ws.tot, c.wave ? 1 : 0, st));
+    const DevWork &w = *c.ws[g];
+    double *final_state = c.wave ? w.state : lane_cur;
+    HIP_TRY(h, launch_scatter(c.N[g], c.npts[g], m.S, m.B, w.meta,
+                              w.slot_point, final_state, w.slot_cap, m.x,
+                              w.tot, c.wave ? 1 : 0, st));
   }
   return FSBM_OK;
 }
@@ -781,6 +810,8 @@ int run_call(const Call &c, void *stream) {
   for (size_t g = 0; g < c.hs.size(); ++g) {
     key.ptrs.push_back(c.N[g]);
     key.ptrs.push_back(c.p[g]);
+    key.ptrs.push_back(g < c.t_old.size() ? c.t_old[g] : nullptr);
+    key.ptrs.push_back(g < c.t_now.size() ? c.t_now[g] : nullptr);
     key.npts.push_back(c.npts[g]);
     key.handles.push_back(c.hs[g]);
     key.gens.push_back(c.hs[g]->gen);
@@ -936,6 +967,14 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
 int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
                    int64_t npoints, double dt_s, int32_t nsteps,
                    void *stream) {
+  return fsbm_coal_step_gated(h, N, p_hpa, nullptr, nullptr, npoints, dt_s,
+                              nsteps, stream);
+}
+
+int fsbm_coal_step_gated(fsbm_coal_t h, double *N, const double *p_hpa,
+                         const double *t_old_k, const double *t_now_k,
+                         int64_t npoints, double dt_s, int32_t nsteps,
+                         void *stream) {
   RC_TRY(check_step_args(h, N, p_hpa, npoints, dt_s, nsteps));
   if (npoints == 0 || nsteps == 0) return FSBM_OK;
   HIP_TRY(h, hipSetDevice(h->device));
@@ -946,7 +985,10 @@ int fsbm_coal_step(fsbm_coal_t h, double *N, const double *p_hpa,
   c.hs = {h};
   c.N = {N};
   c.p = {p_hpa};
+  c.t_old = {t_old_k};
+  c.t_now = {t_now_k};
   c.npts = {npoints};
+  c.ws = {&h->ws};
   c.dt = dt_s;
   c.nsteps = nsteps;
   c.wave = !h->lane;
@@ -997,6 +1039,7 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
       RC_TRY(debug_check(h, c.N[g], c.npts[g], (hipStream_t)stream));
     h->last_npoints = c.npts[g];
   }
+  for (size_t g = 0; g < c.hs.size(); ++g) c.ws.push_back(&c.hs[g]->ws);
   c.dt = dt_s;
   c.nsteps = nsteps;
   c.wave = true;
@@ -1133,10 +1176,11 @@ int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
   if (!h) return FSBM_EINVAL;
   if (h->wpoints < 0 || h->last_npoints == 0) return FSBM_EINVAL;
   const int64_t n = h->last_npoints;
+  const DevWork &w = h->ws;
   double *dst[4] = {mass_before, mass_after, num_before, num_after};
   for (int k = 0; k < 4; ++k)
     if (dst[k])
-      HIP_TRY(h, hipMemcpyAsync(dst[k], h->ws.tot + (size_t)k * n,
+      HIP_TRY(h, hipMemcpyAsync(dst[k], w.tot + (size_t)k * n,
                                 sizeof(double) * n, hipMemcpyDeviceToDevice,
                                 h->last_stream));
   return FSBM_OK;
@@ -1157,8 +1201,9 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   if (h->last_npoints == 0) return FSBM_OK;  // no step since tuning
   unsigned long long c[kNumCounters];
   CompactMeta meta;
-  HIP_TRY(h, hipMemcpy(c, h->ws.counters, sizeof(c), hipMemcpyDeviceToHost));
-  HIP_TRY(h, hipMemcpy(&meta, h->ws.meta, sizeof(meta),
+  const DevWork &w = h->ws;
+  HIP_TRY(h, hipMemcpy(c, w.counters, sizeof(c), hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&meta, w.meta, sizeof(meta),
                        hipMemcpyDeviceToHost));
   out->active_points = meta.nactive;
   out->pair_evals = (int64_t)c[0];

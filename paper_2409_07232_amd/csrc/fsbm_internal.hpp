@@ -113,6 +113,7 @@ __host__ __device__ __forceinline__ size_t state_index_aos(int q, int slot,
 struct DevWork {
   int64_t npoints;
   int slot_cap;          // capacity of the slot arrays (stride of state)
+  int nblocks;           // compaction blocks (rows of block_counts)
   int *slot_point;       // [slot_cap] point index or -1 (padding)
   double *state;         // tiled SoA [slot/64][S*B][slot%64] bin numbers N
   double *state_alt;     // same shape: second buffer of the lane kernels
@@ -124,7 +125,9 @@ struct DevWork {
   unsigned *keys;        // [slot_cap] sort keys (lane kernels) or null
   int *pending;          // [slot_cap] steps of the call left for the exact
                          // FP64 path (0 = point still on the fast path)
-  unsigned char *cloudy;  // [npoints] 1 iff the point holds mass
+  unsigned char *cloudy;  // [npoints] 1: takes part in the call (holds mass,
+                          // passes the temperature gates); 2: holds mass,
+                          // gated; 0: no mass
   unsigned long long *counters;  // [kNumCounters]: pair evals, limiter,
                                  // fallback steps, work-queue position of
                                  // the wave kernel, pair evals of the exact
@@ -175,6 +178,7 @@ hipError_t launch_compact_count(const double *N, const double *p,
                                 int64_t npoints, int SB, const double *plev,
                                 int L, int *block_counts,
                                 unsigned char *cloudy, int nblocks,
+                                const double *t_old, const double *t_now,
                                 hipStream_t st);
 hipError_t launch_compact_scan(const int *block_counts, int *block_offsets,
                                int nblocks, int nbuckets, CompactMeta *meta,
