@@ -156,6 +156,35 @@ int fsbm_coal_step_gated(fsbm_coal_t h, double *N, const double *p_hpa,
                          void *stream);
 
 /*
+ * fsbm_coal_step without any device allocation, for callers that cannot
+ * allocate: code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (bit for bit),
+ * ownership and errors as fsbm_coal_step, except:
+ *  - the call's workspace is a fixed block of 64 MiB (67108864 bytes) of
+ *    static device memory in the library, one per GPU, held from the
+ *    library's first use on that GPU until the process ends.  A call whose
+ *    workspace does not fit returns FSBM_EUNSUPPORTED before enqueueing
+ *    anything (fsbm_coal_last_error gives the bytes needed).  The workspace
+ *    takes about 2 S B 8 + 54 bytes per point on the one-point-per-lane
+ *    kernels (one species on the doubling grid, B <= 40) and S B 8 + 50
+ *    bytes per point otherwise: about 110,000 points at 33 bins and one
+ *    species, 60,000 at four species;
+ *  - the call enqueues kernels only: no allocation, no hipGraph of its own,
+ *    no host synchronisation, so it may itself be captured into a caller's
+ *    graph.  FSBM_FLAG_DEBUG_CHECKS and FSBM_FLAG_PROFILE are ignored;
+ *  - every call on one GPU, from any handle, shares that GPU's block and
+ *    overwrites it: calls that overlap in time on one GPU (different streams
+ *    or threads) race and give undefined results; serialise them.
+ *    fsbm_coal_totals and fsbm_coal_get_stats after such a call read the
+ *    block, so they hold only until the next call of this entry point on
+ *    that GPU.
+ * Also FSBM_EHIP if the block's device address could not be obtained.
+ */
+int fsbm_coal_step_noalloc(fsbm_coal_t h, double *N, const double *p_hpa,
+                           int64_t npoints, double dt_s, int32_t nsteps,
+                           void *stream);
+
+/*
  * One launch sequence over several handles with different grids (mixed
  * 33/66/132-bin batches): the cloudy points of every grid are compacted into
  * one work list and advanced by one persistent kernel per group of fused

@@ -34,7 +34,7 @@ FLAG_PROFILE = 8
 
 # every entry point declared in include/fsbm_coal.h
 EXPORTS = ("fsbm_coal_opts_default", "fsbm_coal_create", "fsbm_coal_step",
-           "fsbm_coal_step_gated",
+           "fsbm_coal_step_gated", "fsbm_coal_step_noalloc",
            "fsbm_coal_step_multi", "fsbm_coal_tune", "fsbm_coal_totals",
            "fsbm_coal_get_stats", "fsbm_coal_destroy", "fsbm_coal_strerror",
            "fsbm_coal_last_error")
@@ -102,6 +102,10 @@ def load(path: str = LIB_PATH):
     lib.fsbm_coal_step_gated.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64,
                                          ctypes.c_double, ctypes.c_int32, vp]
     lib.fsbm_coal_step_gated.restype = ctypes.c_int
+    lib.fsbm_coal_step_noalloc.argtypes = [vp, vp, vp, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_int32,
+                                           vp]
+    lib.fsbm_coal_step_noalloc.restype = ctypes.c_int
     lib.fsbm_coal_step_multi.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                          ctypes.POINTER(vp),
                                          ctypes.POINTER(vp),
@@ -238,6 +242,20 @@ class FsbmCoal:
                                          int(nsteps), _stream_handle(stream))
         if rc != FSBM_OK:
             self._raise(rc, "fsbm_coal_step_gated")
+        self._last_npoints = P
+
+    def step_noalloc(self, N, p, dt: float, nsteps: int, stream=None):
+        """Same as step() through ``fsbm_coal_step_noalloc``: the library's
+        static scratch block is the workspace, nothing is allocated."""
+        _check_state(N, self.nspecies, self.nbins)
+        P = int(N.shape[0])
+        _check_p(p, P)
+        rc = load().fsbm_coal_step_noalloc(self._h, N.data_ptr(),
+                                           p.data_ptr(), P, float(dt),
+                                           int(nsteps),
+                                           _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_step_noalloc")
         self._last_npoints = P
 
     def totals(self):

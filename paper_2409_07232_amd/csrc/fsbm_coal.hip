@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,33 @@ constexpr int kDefaultSteps = 10;
 // persistent blocks of the wave kernel: enough one-wave blocks to fill every
 // SIMD several times over (256 CUs x 4 SIMDs x 8 waves)
 constexpr int kDefaultWaveBlocks = 8192;
+
+// Workspace of fsbm_coal_step_noalloc, for callers that cannot allocate
+// device memory: one block per GPU, held from the library's first use on
+// that GPU until the process ends.  Host code never names the array except
+// to look up its device address (scratch_setup); kernels get that address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of scratch on each GPU, looked up once per device at the
+// first fsbm_coal_create on it (that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? (unsigned char *)ptr : nullptr;
+  if (e != hipSuccess) (void)hipGetLastError();
+  g_scratch_done[device] = true;
+}
 
 // Generation numbers of device allocations baked into captured graphs: a
 // handle takes a new one at create and whenever its workspace is
@@ -80,6 +108,9 @@ struct fsbm_coal_s {
   void *wmem = nullptr;
   int64_t wpoints = -1;  // points the workspace was laid out for
   DevWork ws{};
+  // the last call's workspace was a view of the scratch array (sws)
+  bool last_scratch = false;
+  DevWork sws{};
   // graph cache
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -530,7 +561,9 @@ void drop_graph(fsbm_coal_t h) {
 // Workspace of a call over up to npoints points: slots, state (two buffers
 // for the lane kernels), weights, compaction scratch, totals, counters,
 // pending-step counters, sort keys and cloudy flags, in one block.  The
-// layout depends on the handle's shape and npoints only.
+// layout depends on the handle's shape and npoints only, so the same block
+// can come from hipMalloc (fsbm_coal_step) or from the static scratch array
+// (fsbm_coal_step_noalloc).
 struct WsLayout {
   int cap = 0, nblocks = 0;
   size_t o_state = 0, o_state2 = 0, o_wgt = 0, o_tot = 0, o_slot = 0,
@@ -664,18 +697,27 @@ struct Call {
   std::vector<int64_t> npts;
   double dt = 0.0;
   int nsteps = 0;
-  // workspace of every grid
+  // workspace of every grid: the handle's own, or a view of the static
+  // scratch array (fsbm_coal_step_noalloc)
   std::vector<const DevWork *> ws;
   bool wave = false;  // one-point-per-wave kernel for every grid
+  bool clear_pending = false;  // scratch workspace: clear pending[] first
+  bool allow_profile = true;   // FSBM_FLAG_PROFILE honoured (events)
   int spl = 0, wpb = 0, blocks = 0;
 };
 
 int enqueue_prologue(fsbm_coal_t h, const DevWork &w, double *N,
                      const double *p, const double *t_old,
                      const double *t_now, int64_t npoints, bool aos,
-                     hipStream_t st) {
+                     bool clear_pending, hipStream_t st) {
   const DevModel &m = h->dm;
   HIP_TRY(h, launch_zero_u64(w.counters, kNumCounters, st));
+  // pending[] starts the call at zero; the handle's own workspace keeps it
+  // there between calls, a shared scratch block does not (a fill kernel,
+  // not a memset node, since the caller may be capturing the stream)
+  if (clear_pending)
+    HIP_TRY(h, launch_zero_u64((unsigned long long *)w.pending,
+                               w.slot_cap / 2, st));
   HIP_TRY(h, launch_compact_count(N, p, npoints, m.S * m.B, m.plev, m.L,
                                   w.block_counts, w.cloudy, w.nblocks,
                                   t_old, t_now, st));
@@ -702,8 +744,9 @@ int enqueue_call(const Call &c, hipStream_t st) {
     RC_TRY(enqueue_prologue(c.hs[g], *c.ws[g], c.N[g], c.p[g],
                             g < c.t_old.size() ? c.t_old[g] : nullptr,
                             g < c.t_now.size() ? c.t_now[g] : nullptr,
-                            c.npts[g], c.wave, st));
-  const bool prof = (h0->flags & FSBM_FLAG_PROFILE) != 0;
+                            c.npts[g], c.wave, c.clear_pending, st));
+  const bool prof =
+      c.allow_profile && (h0->flags & FSBM_FLAG_PROFILE) != 0;
   const DevWork &w0 = *c.ws[0];
   StepArgs la{};
   WaveArgs wa{};
@@ -954,6 +997,7 @@ int fsbm_coal_create(int32_t nbins, int32_t nspecies,
             !(o.flags & FSBM_FLAG_FORCE_WAVE);
   h->order = o.order;
   h->gen = ++g_generation;
+  scratch_setup(h->device);
   read_tune_cache(h);
   const int rc = build_model(h, kernel_tables, p_levels_hpa);
   if (rc != FSBM_OK) {
@@ -996,7 +1040,56 @@ int fsbm_coal_step_gated(fsbm_coal_t h, double *N, const double *p_hpa,
   c.wpb = waves_per_block(h);
   c.blocks = wave_blocks(h);
   h->last_npoints = npoints;
+  h->last_scratch = false;
   return run_call(c, stream);
+}
+
+int fsbm_coal_step_noalloc(fsbm_coal_t h, double *N, const double *p_hpa,
+                           int64_t npoints, double dt_s, int32_t nsteps,
+                           void *stream) {
+  RC_TRY(check_step_args(h, N, p_hpa, npoints, dt_s, nsteps));
+  if (npoints == 0 || nsteps == 0) return FSBM_OK;
+  HIP_TRY(h, hipSetDevice(h->device));
+  unsigned char *base = nullptr;
+  hipError_t serr = hipErrorInvalidDevice;
+  if (h->device >= 0 && h->device < kMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[h->device];
+    serr = g_scratch_err[h->device];
+  }
+  if (!base)
+    return hip_fail(h, serr == hipSuccess ? hipErrorInvalidDevice : serr,
+                    "fsbm_coal_step_noalloc: scratch address");
+  WsLayout L;
+  RC_TRY(ws_layout(h, npoints, L));
+  if (L.bytes > kScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof(msg),
+             "fsbm_coal_step_noalloc: %lld points need %zu bytes of "
+             "workspace; the scratch array holds %zu",
+             (long long)npoints, L.bytes, kScratchBytes);
+    h->last_error = msg;
+    return FSBM_EUNSUPPORTED;
+  }
+  ws_bind(h, L, base, npoints, h->sws);
+  Call c;
+  c.hs = {h};
+  c.N = {N};
+  c.p = {p_hpa};
+  c.npts = {npoints};
+  c.ws = {&h->sws};
+  c.dt = dt_s;
+  c.nsteps = nsteps;
+  c.wave = !h->lane;
+  c.clear_pending = true;
+  c.allow_profile = false;
+  c.spl = steps_per_launch(h);
+  c.wpb = waves_per_block(h);
+  c.blocks = wave_blocks(h);
+  h->last_npoints = npoints;
+  h->last_scratch = true;
+  h->last_stream = (hipStream_t)stream;
+  return enqueue_call(c, (hipStream_t)stream);
 }
 
 int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
@@ -1038,6 +1131,7 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
     if (h->flags & FSBM_FLAG_DEBUG_CHECKS)
       RC_TRY(debug_check(h, c.N[g], c.npts[g], (hipStream_t)stream));
     h->last_npoints = c.npts[g];
+    h->last_scratch = false;
   }
   for (size_t g = 0; g < c.hs.size(); ++g) c.ws.push_back(&c.hs[g]->ws);
   c.dt = dt_s;
@@ -1174,9 +1268,10 @@ int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
 int fsbm_coal_totals(fsbm_coal_t h, double *mass_before, double *mass_after,
                      double *num_before, double *num_after) {
   if (!h) return FSBM_EINVAL;
-  if (h->wpoints < 0 || h->last_npoints == 0) return FSBM_EINVAL;
+  if ((h->wpoints < 0 && !h->last_scratch) || h->last_npoints == 0)
+    return FSBM_EINVAL;
   const int64_t n = h->last_npoints;
-  const DevWork &w = h->ws;
+  const DevWork &w = h->last_scratch ? h->sws : h->ws;
   double *dst[4] = {mass_before, mass_after, num_before, num_after};
   for (int k = 0; k < 4; ++k)
     if (dst[k])
@@ -1193,7 +1288,7 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   out->steps_per_launch = steps_per_launch(h);
   out->waves_per_block = h->lane ? waves_per_block(h) : 1;
   out->graph_captures = h->graph_captures;
-  if (h->wpoints < 0) return FSBM_OK;
+  if (h->wpoints < 0 && !h->last_scratch) return FSBM_OK;
   HIP_TRY(h, hipStreamSynchronize(h->last_stream));
   RC_TRY(harvest_events(h));
   out->kernel_launches = h->prof_launches;
@@ -1201,7 +1296,7 @@ int fsbm_coal_get_stats(fsbm_coal_t h, fsbm_coal_stats *out) {
   if (h->last_npoints == 0) return FSBM_OK;  // no step since tuning
   unsigned long long c[kNumCounters];
   CompactMeta meta;
-  const DevWork &w = h->ws;
+  const DevWork &w = h->last_scratch ? h->sws : h->ws;
   HIP_TRY(h, hipMemcpy(c, w.counters, sizeof(c), hipMemcpyDeviceToHost));
   HIP_TRY(h, hipMemcpy(&meta, w.meta, sizeof(meta),
                        hipMemcpyDeviceToHost));
