@@ -60,9 +60,15 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 # summary under profiles/ gives the commands).  They hold only for the
 # kernel sources they were taken on: the SHA-256 of the concatenated files
 # below must match, otherwise the traffic entry is reported as null.
-TRAFFIC_SOURCES = ("kernels_lane.hip", "device_common.hpp")
+TRAFFIC_SOURCES = ("kernels_lane.hip", "device_common.hpp", "slow_path.hpp")
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, bytes per launch, profile summary)
+    "lane_step_f32c<33>": (
+        "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
+        4.0693e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+    "lane_step_f64<33>": (
+        "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
+        2.8413e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
 }
 
 
@@ -114,6 +120,8 @@ def kernel_name(st, precision, nbins):
         return "lane_seq_f64<%d>" % nbins
     if st["kernel"] == 0:
         return "lane_step_%s<%d>" % ("f32c" if f32 else "f64", nbins)
+    if st["kernel"] == 3:
+        return "lane_multi_f32c<%d,NS=1..4>" % nbins
     return "wave_step<%s>" % ("F32" if f32 else "F64")
 
 
