@@ -42,9 +42,12 @@ extern "C" {
                         per bin in FP64 (each enters exactly, so a transfer
                         leaves and enters with the same value); FP64 final
                         update.  From a point's first step that needs the
-                        positivity limiter (or, one point per wave, would
+                        positivity limiter (or, several species, would
                         drain a bin by more than half), its remaining steps
-                        of the call run in FP64. */
+                        of the call run in FP64.  Two to four species on
+                        the doubling grid with 33 bins run one point per
+                        lane (points grouped by the species they hold),
+                        other shapes one point per wave. */
 
 /* update order of the pairs within a step */
 #define FSBM_ORDER_SIMULTANEOUS 0 /* every pair from the step's start state,
@@ -202,9 +205,16 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
                          void *stream);
 
 /*
- * Explicitly autotune the launch shape (steps per launch, waves per block)
- * for about npoints_hint cloudy points, timing candidates on synthetic
- * states; every candidate is checked against the default shape first.
+ * Explicitly autotune the kernel family and launch shape for about
+ * npoints_hint cloudy points, timing candidates on synthetic states.
+ * Candidates: steps per launch and waves per block (one point per lane);
+ * where the several-species lane kernels apply (FP32C, two to four species,
+ * doubling grid, 33 bins), those and the one-point-per-wave kernel, each
+ * with steps per launch (and persistent blocks); the fastest one that
+ * passes the checks is kept.  Within a family every candidate must repeat
+ * the family's first result bit for bit; a second family must agree with
+ * the first within 2e-5 of each bin's mass (fsbm_coal_stats counts
+ * candidates run and rejected).
  * Synchronises the stream.  The choice is kept in the handle and in the
  * cache file named by the FSBM_TUNE_CACHE environment variable, if set.
  * The synthetic runs use the handle's workspace: until the next step,
@@ -241,8 +251,11 @@ typedef struct {
                                   limiter fires the point takes that and
                                   every remaining step of the call in FP64
                                   mode */
-  int32_t kernel;         /* 0 = one point per lane, 1 = one point per
-                             wave, 2 = one point per lane, sequential */
+  int32_t kernel;         /* kernel family of the last call (before any
+                             call: the one a call would use): 0 = one
+                             point per lane, 1 = one point per wave, 2 =
+                             one point per lane, sequential, 3 = one point
+                             per lane for two to four species (FP32C) */
   int32_t steps_per_launch;
   int32_t waves_per_block;
   int32_t kernel_launches; /* FSBM_FLAG_PROFILE: collision-kernel launches
@@ -256,6 +269,13 @@ typedef struct {
                               cached graph only while the call's
                               arguments, launch shape and the workspaces
                               of every handle in it are unchanged */
+  int32_t tune_candidates; /* the last fsbm_coal_tune: candidates run */
+  int32_t tune_rejected;   /* ... and rejected: a launch shape whose result
+                              differs from its family's first candidate by
+                              a bit, or a kernel family whose result
+                              differs from the first family's by more than
+                              2e-5 of a bin's mass (floor 1e-9 of the
+                              point's mass) */
 } fsbm_coal_stats;
 
 /* Counters of the last step call.  Synchronises that call's stream. */

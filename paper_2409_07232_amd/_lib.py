@@ -71,7 +71,9 @@ class Stats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double),
                 ("exact_pair_evals", ctypes.c_int64),
-                ("graph_captures", ctypes.c_int64)]
+                ("graph_captures", ctypes.c_int64),
+                ("tune_candidates", ctypes.c_int32),
+                ("tune_rejected", ctypes.c_int32)]
 
 
 _lib = None

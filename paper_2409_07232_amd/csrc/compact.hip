@@ -60,16 +60,26 @@ __device__ __forceinline__ void bracket_of(const double *plev, int L,
   w = (p - plev[b + 1]) / (plev[b] - plev[b + 1]);
 }
 
-// Cloudy flags and per-bracket counts of one block of points.  Flag 1: the
-// point holds mass and passes the temperature gates (t_old, t_now; a null
-// array passes its test), so it takes part in the call; flag 2: it holds
-// mass but a gate stops it (left unchanged, totals still recorded); flag 0:
-// no mass.  The block's
-// rows are one contiguous run of S*B doubles per point: its threads read
-// the run with consecutive addresses (one wave load covers 512 bytes) and
-// mark the point of every positive entry in LDS; the point of entry e is
-// e / SB, taken as the high word of e * magic with magic = ceil(2^32 / SB),
-// exact for every e < 256 SB.  Then each thread counts its own point.
+// Flag of a point in the per-point byte array left by compact_count.
+constexpr unsigned char kFlagDry = 0;     // no mass
+constexpr unsigned char kFlagGated = 255; // mass, stopped by a temperature
+                                          // gate: unchanged, totals kept
+// any other value: 1 + the point's bucket; it takes part in the call
+__device__ __forceinline__ bool flag_active(unsigned char f) {
+  return f != kFlagDry && f != kFlagGated;
+}
+
+// Cloudy flags and per-bucket counts of one block of points.  A point takes
+// part in the call if it holds mass and passes the temperature gates
+// (t_old, t_now; a null array passes its test).  Its bucket is its pressure
+// bracket l, or with nmask > 1 (multi-species lane kernels) l * nmask + the
+// closure of the set of species holding mass.  The block's rows are one
+// contiguous run of S*B doubles per point: its threads read the run with
+// consecutive addresses (one wave load covers 512 bytes) and mark the point
+// of every positive entry in LDS (with nmask > 1, the entry's species bit);
+// the point of entry e is e / SB, taken as the high word of e * magic with
+// magic = ceil(2^32 / SB), exact for every e < 256 SB.  Then each thread
+// counts its own point.
 __global__ void __launch_bounds__(kCompactThreads)
     compact_count(const double *__restrict__ N, const double *__restrict__ p,
                   int64_t npoints, int SB, unsigned magic,
@@ -77,12 +87,15 @@ __global__ void __launch_bounds__(kCompactThreads)
                   int *__restrict__ block_counts,
                   unsigned char *__restrict__ cloudy,
                   const double *__restrict__ t_old,
-                  const double *__restrict__ t_now) {
+                  const double *__restrict__ t_now, int B, int nmask,
+                  const unsigned char *__restrict__ closure) {
   __shared__ int cnt[kMaxBuckets];
   __shared__ unsigned char wet[kCompactThreads];
+  __shared__ unsigned spec[kCompactThreads];
   const int t = threadIdx.x;
   if (t < kMaxBuckets) cnt[t] = 0;
   wet[t] = 0;
+  spec[t] = 0u;
   __syncthreads();
   // the grid covers the workspace's capacity: blocks past this call's
   // points have no rows (np = 0) and count zero
@@ -102,7 +115,12 @@ __global__ void __launch_bounds__(kCompactThreads)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const unsigned e = e0 + u * kCompactThreads;
-      if (v[u] > 0.0) wet[__umulhi(e, magic)] = 1;
+      if (v[u] > 0.0) {
+        const unsigned pt = __umulhi(e, magic);
+        wet[pt] = 1;
+        if (nmask > 1)
+          atomicOr(&spec[pt], 1u << ((e - pt * (unsigned)SB) / (unsigned)B));
+      }
     }
   }
   __syncthreads();
@@ -112,13 +130,16 @@ __global__ void __launch_bounds__(kCompactThreads)
     // a NaN temperature fails its test
     if (c && t_old) c = t_old[p0 + t] > kTOldMin;
     if (c && t_now) c = t_now[p0 + t] > kTCollMin;
-    cloudy[p0 + t] = c ? 1 : (has_mass ? 2 : 0);
+    unsigned char f = has_mass ? kFlagGated : kFlagDry;
     if (c) {
       int l;
       double w;
       bracket_of(plev, L, p[p0 + t], l, w);
-      atomicAdd(&cnt[l], 1);
+      const int bk = nmask > 1 ? l * nmask + closure[spec[t]] : l;
+      atomicAdd(&cnt[bk], 1);
+      f = (unsigned char)(1 + bk);
     }
+    cloudy[p0 + t] = f;
   }
   __syncthreads();
   if (t < kMaxBuckets)
@@ -182,7 +203,8 @@ __global__ void __launch_bounds__(kCompactThreads)
                    double *__restrict__ wgt, int slot_cap,
                    const double *__restrict__ x, double *__restrict__ tot,
                    int aos, unsigned *__restrict__ keys, double theta,
-                   const unsigned char *__restrict__ cloudy_flag) {
+                   const unsigned char *__restrict__ cloudy_flag,
+                   int nbuckets) {
   constexpr int kWaves = kCompactThreads / kWave;
   __shared__ int wave_cnt[kWaves][kMaxBuckets];
   const int SB = S * B;
@@ -191,16 +213,20 @@ __global__ void __launch_bounds__(kCompactThreads)
   const int64_t pt = (int64_t)blockIdx.x * kCompactThreads + threadIdx.x;
   const bool inside = pt < npoints;
   const double *row = N + (inside ? pt : 0) * SB;
-  const bool cloudy = inside && cloudy_flag[pt] == 1;
+  const unsigned char flag = inside ? cloudy_flag[pt] : kFlagDry;
+  const bool cloudy = flag_active(flag);
   // gated points keep their mass: their totals are still recorded
-  const bool has_mass = inside && cloudy_flag[pt] != 0;
-  int l = 0;
+  const bool has_mass = flag != kFlagDry;
+  int l = 0, br = 0;
   double w = 0.0;
-  if (cloudy) bracket_of(plev, L, p[pt], l, w);
-  // stable rank of this point among the block's cloudy points of bracket l
+  if (cloudy) {
+    bracket_of(plev, L, p[pt], br, w);
+    l = flag - 1;  // the point's bucket
+  }
+  // stable rank of this point among the block's cloudy points of bucket l
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   int rank = 0;
-  for (int bk = 0; bk < kMaxBuckets; ++bk) {
+  for (int bk = 0; bk < nbuckets; ++bk) {
     const uint64_t m = __ballot(cloudy && l == bk);
     if (lane == 0) wave_cnt[wv][bk] = __popcll(m);
     if (cloudy && l == bk) rank = __popcll(m & lt_mask);
@@ -215,6 +241,7 @@ __global__ void __launch_bounds__(kCompactThreads)
         m += v * x[k];
         n += v;
       }
+  (void)br;
   if (cloudy) {
     int before = 0;
     for (int v = 0; v < wv; ++v) before += wave_cnt[v][l];
@@ -224,17 +251,17 @@ __global__ void __launch_bounds__(kCompactThreads)
     slot_point[slot] = (int)pt;
     wgt[slot] = w;
     if (keys) {
-      // sort key: bracket, top active bin, top 16 bits of the total mass
-      // (positive doubles order like their bit patterns); the state is
-      // loaded after the sort.  Keys exist for one species only (q = bin),
-      // where m is the total mass.
+      // sort key: bucket, top active bin over the species, top 16 bits of
+      // the total mass (positive doubles order like their bit patterns);
+      // the state is loaded after the sort
       const double mt = m;
       int top = 0;
-      for (int q = SB - 1; q > 0; --q)
-        if (row[q] * x[q] >= theta * mt && row[q] > 0.0) {
-          top = q;
-          break;
-        }
+      for (int a = 0; a < S; ++a)
+        for (int k = B - 1; k > top; --k)
+          if (row[a * B + k] * x[k] >= theta * mt && row[a * B + k] > 0.0) {
+            top = k;
+            break;
+          }
       const unsigned long long bits =
           (unsigned long long)__double_as_longlong(mt);
       keys[slot] = ((unsigned)l << 24) | ((unsigned)min(top, 255) << 16) |
@@ -320,16 +347,18 @@ __global__ void __launch_bounds__(kSortThreads)
   }
 }
 
-// Tiled staging of the one-point-per-lane path (one species, at most
-// kTileBins bins): a wave moves the 64 points of one tile, each point's row
-// of the caller's array with one coalesced access (lane = bin), transposed
-// through LDS into the tile's rows (lane = slot).  A bounded grid strides
-// over the tiles, since only the device knows how many slots are filled.
+// Tiled staging of the one-point-per-lane paths (at most kMultiMaxSB bins
+// per point): a wave moves the 64 points of one tile, each chunk of up to
+// kTileBins bins of a point's row of the caller's array with one coalesced
+// access (lane = bin), transposed through LDS into the tile's rows (lane =
+// slot).  A bounded grid strides over the tiles, since only the device
+// knows how many slots are filled.
 constexpr int kTileBins = 64;
 constexpr int kTilePitch = kWave + 1;  // LDS row pitch (doubles)
 constexpr int kTileGridMax = 16384;
 
-// State of every compacted point into its (sorted) slot, tiled layout.
+// State of every compacted point into its (sorted) slot, tiled layout;
+// bins in chunks of kTileBins (lane = bin within the chunk).
 __global__ void __launch_bounds__(kWave)
     compact_load(const double *__restrict__ N,
                  const CompactMeta *__restrict__ meta,
@@ -340,32 +369,37 @@ __global__ void __launch_bounds__(kWave)
   const int nslots = meta->nslots;
   constexpr int kBatch = 8;  // rows whose loads are in flight together
   for (int t0 = blockIdx.x * kWave; t0 < nslots; t0 += gridDim.x * kWave) {
-    for (int r0 = 0; r0 < kWave; r0 += kBatch) {
-      double v[kBatch];
-      int pr[kBatch];
+    for (int c0 = 0; c0 < SB; c0 += kTileBins) {
+      const int q = c0 + lane;
+      for (int r0 = 0; r0 < kWave; r0 += kBatch) {
+        double v[kBatch];
+        int pr[kBatch];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int slot = t0 + r0 + u;
-        pr[u] = slot < nslots ? slot_point[slot] : -1;
-        v[u] = (pr[u] >= 0 && lane < SB) ? N[(int64_t)pr[u] * SB + lane] : 0.0;
+        for (int u = 0; u < kBatch; ++u) {
+          const int slot = t0 + r0 + u;
+          pr[u] = slot < nslots ? slot_point[slot] : -1;
+          v[u] = (pr[u] >= 0 && q < SB) ? N[(int64_t)pr[u] * SB + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (pr[u] >= 0 && q < SB) tile[lane * kTilePitch + r0 + u] = v[u];
       }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (pr[u] >= 0 && lane < SB) tile[lane * kTilePitch + r0 + u] = v[u];
+      __syncthreads();
+      const int slot = t0 + lane;
+      const int nq = min(kTileBins, SB - c0);
+      if (slot < nslots && slot_point[slot] >= 0)
+        for (int r = 0; r < nq; ++r)
+          state[state_index(c0 + r, slot, SB)] = tile[r * kTilePitch + lane];
+      __syncthreads();
     }
-    __syncthreads();
-    const int slot = t0 + lane;
-    if (slot < nslots && slot_point[slot] >= 0)
-      for (int q = 0; q < SB; ++q)
-        state[state_index(q, slot, SB)] = tile[q * kTilePitch + lane];
-    __syncthreads();
   }
 }
 
 // Tiled state back into the caller's array (the reverse of compact_load),
-// with each point's FP64 totals after the call (bins in ascending order).
+// with each point's FP64 totals after the call (species, then bins in
+// ascending order).
 __global__ void __launch_bounds__(kWave)
-    scatter_tiled(double *__restrict__ N, int SB,
+    scatter_tiled(double *__restrict__ N, int SB, int B,
                   const CompactMeta *__restrict__ meta,
                   const int *__restrict__ slot_point,
                   const double *__restrict__ state,
@@ -377,27 +411,30 @@ __global__ void __launch_bounds__(kWave)
   for (int t0 = blockIdx.x * kWave; t0 < nslots; t0 += gridDim.x * kWave) {
     const int slot = t0 + lane;
     const int pt = slot < nslots ? slot_point[slot] : -1;
-    if (pt >= 0) {
-      double m = 0.0, n = 0.0;
-      for (int q = 0; q < SB; ++q) {
-        const double v = state[state_index(q, slot, SB)];
-        tile[q * kTilePitch + lane] = v;
-        m += v * x[q];
-        n += v;
+    double m = 0.0, n = 0.0;
+    for (int c0 = 0; c0 < SB; c0 += kTileBins) {
+      const int nq = min(kTileBins, SB - c0);
+      if (pt >= 0)
+        for (int r = 0; r < nq; ++r) {
+          const int q = c0 + r;
+          const double v = state[state_index(q, slot, SB)];
+          tile[r * kTilePitch + lane] = v;
+          m += v * x[q % B];
+          n += v;
+        }
+      __syncthreads();
+      for (int r = 0; r < kWave; ++r) {
+        const int sr = t0 + r;
+        const int pr = sr < nslots ? slot_point[sr] : -1;
+        if (pr >= 0 && lane < nq)
+          N[(int64_t)pr * SB + c0 + lane] = tile[lane * kTilePitch + r];
       }
-      if (tot) {
-        tot[(size_t)npoints + pt] = m;
-        tot[3 * (size_t)npoints + pt] = n;
-      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int r = 0; r < kWave; ++r) {
-      const int sr = t0 + r;
-      const int pr = sr < nslots ? slot_point[sr] : -1;
-      if (pr >= 0 && lane < SB)
-        N[(int64_t)pr * SB + lane] = tile[lane * kTilePitch + r];
+    if (pt >= 0 && tot) {
+      tot[(size_t)npoints + pt] = m;
+      tot[3 * (size_t)npoints + pt] = n;
     }
-    __syncthreads();
   }
 }
 
@@ -452,6 +489,8 @@ hipError_t launch_compact_count(const double *N, const double *p,
                                 int L, int *block_counts,
                                 unsigned char *cloudy, int nblocks,
                                 const double *t_old, const double *t_now,
+                                int B, int nmask,
+                                const unsigned char *closure,
                                 hipStream_t st) {
   if (SB < 1 || SB > kWave * kMaxOwn ||
       npoints > (int64_t)nblocks * kCompactThreads)
@@ -459,7 +498,7 @@ hipError_t launch_compact_count(const double *N, const double *p,
   const unsigned magic = 0xffffffffu / (unsigned)SB + 1u;
   hipLaunchKernelGGL(compact_count, dim3(nblocks), dim3(kCompactThreads), 0,
                      st, N, p, npoints, SB, magic, plev, L, block_counts,
-                     cloudy, t_old, t_now);
+                     cloudy, t_old, t_now, B, nmask, closure);
   return hipGetLastError();
 }
 
@@ -479,19 +518,21 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  int *slot_point, double *state, double *wgt,
                                  int slot_cap, const double *x, double *tot,
                                  int aos, unsigned *keys, double theta,
-                                 const unsigned char *cloudy,
+                                 const unsigned char *cloudy, int nbuckets,
                                  hipStream_t st) {
   hipLaunchKernelGGL(compact_gather, dim3(nblocks), dim3(kCompactThreads), 0,
                      st, N, p, npoints, S, B, plev, L, block_offsets, meta,
                      slot_point, state, wgt, slot_cap, x, tot, aos, keys,
-                     theta, cloudy);
+                     theta, cloudy, nbuckets);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
-                               unsigned *keys, int slot_cap, hipStream_t st) {
+                               unsigned *keys, int slot_cap, int nbuckets,
+                               hipStream_t st) {
   (void)slot_cap;
-  hipLaunchKernelGGL(fill_padding, dim3(kMaxBuckets), dim3(kWave), 0, st,
+  if (nbuckets < 1 || nbuckets > kMaxBuckets) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_padding, dim3(nbuckets), dim3(kWave), 0, st,
                      meta, slot_point, keys);
   return hipGetLastError();
 }
@@ -507,7 +548,7 @@ hipError_t launch_compact_sort_load(const double *N, const CompactMeta *meta,
                      meta, keys, slot_point, wgt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (SB < 1 || SB > kTileBins) return hipErrorInvalidValue;
+  if (SB < 1 || SB > kMultiMaxSB) return hipErrorInvalidValue;
   const int blocks = std::min((slot_cap + kWave - 1) / kWave, kTileGridMax);
   hipLaunchKernelGGL(compact_load, dim3(blocks), dim3(kWave), 0, st, N, meta,
                      slot_point, SB, state);
@@ -519,12 +560,12 @@ hipError_t launch_scatter(double *N, int64_t npoints, int S, int B,
                           const double *state, int slot_cap, const double *x,
                           double *tot, int aos, hipStream_t st) {
   if (!aos) {
-    // tiled layout: the one-point-per-lane path (one species)
-    if (S != 1 || B > kTileBins) return hipErrorInvalidValue;
+    // tiled layout: the one-point-per-lane paths
+    if (S * B > kMultiMaxSB) return hipErrorInvalidValue;
     const int blocks =
         std::min((slot_cap + kWave - 1) / kWave, kTileGridMax);
-    hipLaunchKernelGGL(scatter_tiled, dim3(blocks), dim3(kWave), 0, st, N, B,
-                       meta, slot_point, state, x, tot, npoints);
+    hipLaunchKernelGGL(scatter_tiled, dim3(blocks), dim3(kWave), 0, st, N,
+                       S * B, B, meta, slot_point, state, x, tot, npoints);
     return hipGetLastError();
   }
   const int blocks = (slot_cap + kCompactThreads - 1) / kCompactThreads;

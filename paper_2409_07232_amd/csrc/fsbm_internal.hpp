@@ -15,11 +15,17 @@ constexpr float kLn2f = 0.69314718055994530942f;
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxSpecies = 8;
 constexpr int kMaxBins = 512;
-constexpr int kMaxBuckets = 8;     // pressure brackets (levels - 1), capped
+constexpr int kMaxBrackets = 8;    // pressure brackets (levels - 1), capped
+// compaction buckets: pressure brackets, or (multi-species lane kernels)
+// pairs of a bracket and a species set
+constexpr int kMaxBuckets = 64;
 constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
 constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
 constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
+// one-point-per-lane kernels for several species: species and S*B limits
+constexpr int kMultiMaxSpecies = 4;
+constexpr int kMultiMaxSB = 132;
 constexpr int kNumCounters = 5;    // device counters of a step call
 // Empty-neighbour guard of the flux fraction: x1 >= ln(1e-60).
 constexpr double kX1Floor = -138.15510557964274;
@@ -28,6 +34,8 @@ constexpr double kX1Floor = -138.15510557964274;
 struct DevModel {
   int B, S, L, s;
   int nbr;        // pressure brackets = max(L - 1, 1)
+  int nmask;      // compaction buckets per bracket: 1, or 2^S where the
+                  // multi-species lane kernels bucket points by species set
   int npairs;     // S (S + 1) / 2 species pairs
   unsigned bmagic;  // ceil(2^32 / B): q / B = umulhi(q, bmagic) for q < 2^32 / B
   double theta;
@@ -52,6 +60,15 @@ struct DevModel {
   // is nonzero at some tabulated level; a pair whose entry is zero at every
   // level collides nothing (C = 0) and is neither evaluated nor counted
   const unsigned long long *nzT;  // [B]
+  // ordered species pairs (a at the smaller bin i, b at the larger bin j),
+  // index a * S + b: kernel entries transposed to [nbr][j][i][2] (FP32,
+  // multi-species lane kernels only) and, for B <= 64, bit i of row j set
+  // iff the entry is nonzero at some level
+  const float *KfO;
+  const unsigned long long *nzO;  // [S * S][B]
+  // [2^S]: the species set a point can hold during a call, from the set it
+  // holds (closed under the product map)
+  const unsigned char *closure;
   // one-point-per-wave kernel: bins of each lane's per-bin work ([64]
   // [kMaxOwn], -1 padded) and two streams of pair entries, gain entries
   // (grouped by the bin the pair lands in) and loss entries (grouped by the
@@ -143,6 +160,8 @@ struct WaveGrid {
   const CompactMeta *meta;
   int *pending;
   int slot_cap;
+  int tiled;      // state in the tiled layout of the one-point-per-lane
+                  // kernels (the FP64 follow-up of the multi-species ones)
 };
 
 struct WaveArgs {
@@ -171,14 +190,19 @@ struct StepArgs {
   double dt;
   int nsteps;           // steps in this launch
   int steps_left;       // steps of the call left when this launch starts
+  int first_launch;     // the call's first launch
 };
 
 // --- host-side launchers (defined in the kernel translation units) -------
+// nmask > 1: points are bucketed by bracket and species set (closure of
+// the species holding mass), B bins per species.
 hipError_t launch_compact_count(const double *N, const double *p,
                                 int64_t npoints, int SB, const double *plev,
                                 int L, int *block_counts,
                                 unsigned char *cloudy, int nblocks,
                                 const double *t_old, const double *t_now,
+                                int B, int nmask,
+                                const unsigned char *closure,
                                 hipStream_t st);
 hipError_t launch_compact_scan(const int *block_counts, int *block_offsets,
                                int nblocks, int nbuckets, CompactMeta *meta,
@@ -192,10 +216,11 @@ hipError_t launch_compact_gather(const double *N, const double *p,
                                  double *wgt, int slot_cap,
                                  const double *x, double *tot, int aos,
                                  unsigned *keys, double theta,
-                                 const unsigned char *cloudy,
+                                 const unsigned char *cloudy, int nbuckets,
                                  hipStream_t st);
 hipError_t launch_fill_padding(const CompactMeta *meta, int *slot_point,
-                               unsigned *keys, int slot_cap, hipStream_t st);
+                               unsigned *keys, int slot_cap, int nbuckets,
+                               hipStream_t st);
 // With keys: order the compacted slots by key within chunks, then load the
 // state (tiled layout) in that order.
 hipError_t launch_compact_sort_load(const double *N, const CompactMeta *meta,
@@ -220,6 +245,14 @@ hipError_t launch_lane_step(const StepArgs &a, int precision,
 // in the FP64 follow-up launch with pending_only set).
 hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
                             hipStream_t st);
+
+// One-point-per-lane FP32C kernels for two to four species on the doubling
+// grid (slots bucketed by bracket and species set, tiled state, double
+// buffered); a point they hand over (pending) finishes the call in the
+// one-point-per-wave kernel's FP64 mode.
+bool multi_kernel_supported(int B, int S, int s, int nbr);
+hipError_t launch_multi_step(const StepArgs &a, int max_slots,
+                             hipStream_t st);
 
 // One-point-per-lane kernel of the sequential (in-place) form: one species,
 // mass-doubling grid, FP64; updates the state in place (a.state).

@@ -203,8 +203,8 @@ struct PassLds {
 // limiter is needed (the caller takes that step in FP64 mode).
 template <bool F32>
 __device__ unsigned point_step(const DevModel &m, const short *own_in,
-                               double *st, double w, int br, double dt,
-                               unsigned char *lds,
+                               double *st, int qs, double w, int br,
+                               double dt, unsigned char *lds,
                                unsigned long long &npairs) {
   // owned bins, opaque per step: keeps the compiler from holding per-bin
   // addresses in registers across steps
@@ -247,7 +247,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     const int q = own[o];
     const unsigned qq = q < 0 ? 0u : (unsigned)q;
     const unsigned k = qq - __umulhi(qq, m.bmagic) * (unsigned)B;
-    no[o] = q < 0 ? 0.0 : st[qq];
+    no[o] = q < 0 ? 0.0 : st[(size_t)qq * qs];
     xo[o] = m.x[k];
   }
   double part = 0.0;
@@ -582,9 +582,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     double net = gq - P.read(P.loss, q);
     if constexpr (F32) net *= Mtot;
     const double xq = m.x[k];
-    double Mn = st[q] * xq + net;
+    double Mn = st[(size_t)q * qs] * xq + net;
     Mn = Mn < 0.0 ? 0.0 : Mn;
-    st[q] = Mn / xq;
+    st[(size_t)q * qs] = Mn / xq;
   }
   __syncthreads();  // LDS is rewritten by the next step
   return lim ? 1u : 0u;
@@ -603,14 +603,22 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
                                            unsigned long long &nfp64) {
   const DevModel &m = G.m;
   const int SB = m.S * m.B;
-  int br = 0;
-  for (int b = 1; b < m.nbr; ++b)
-    if (slot >= G.meta->bucket_base[b]) br = b;
+  // bucket of the slot: its pressure bracket, or (points of the
+  // multi-species lane kernels) bracket x species set
+  const int nmask = G.tiled ? m.nmask : 1;
+  int bk = 0;
+  for (int b = 1; b < m.nbr * nmask; ++b)
+    if (slot >= G.meta->bucket_base[b]) bk = b;
+  const int br = bk / nmask;
   const double w = G.wgt[slot];
-  double *st = G.state + (size_t)slot * SB;
+  // a point's bins: contiguous, or (tiled) 64 slots apart
+  double *st = G.tiled ? G.state + state_index(0, slot, SB)
+                       : G.state + (size_t)slot * SB;
+  const int qs = G.tiled ? kWave : 1;
   const int n = a.pending_only ? pend : a.nsteps;
   for (int step = 0; step < n; ++step) {
-    const unsigned r = point_step<F32>(m, own, st, w, br, a.dt, lds, npairs);
+    const unsigned r =
+        point_step<F32>(m, own, st, qs, w, br, a.dt, lds, npairs);
     if (F32 && r == 2u) {
       if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
       break;

@@ -66,6 +66,23 @@ class Limited:
         return np.where(self.bins, LIMITED_FLOOR, FLOOR)
 
 
+def expected_kernel(w, precision, force_wave=False):
+    """Kernel family a handle of workload w runs (fsbm_coal_stats.kernel):
+    0 one point per lane (one species, doubling grid, B in 3/8/16/33/40),
+    3 one point per lane for two to four species (FP32C, doubling grid, 33
+    bins, pressure brackets x species sets within 64 buckets), else 1 (one
+    point per wave)."""
+    nbr = max(len(w.p_levels) - 1, 1)
+    if force_wave:
+        return 1
+    if w.nspecies == 1 and w.s == 1 and w.nbins in (3, 8, 16, 33, 40):
+        return 0
+    if (precision == 1 and 2 <= w.nspecies <= 4 and w.s == 1 and
+            w.nbins == 33 and nbr * (1 << w.nspecies) <= 64):
+        return 3
+    return 1
+
+
 def model_of(w, order=0):
     return oracle.OracleModel(w.nbins, w.nspecies, w.tables, w.p_levels,
                               w.product, x1_g=w.x1_g, s=w.s, theta=w.theta,

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07232_amd import workloads as wl
-from tests.parity import check, model_of, run_oracle, Limited
+from tests.parity import check, expected_kernel, model_of, run_oracle, Limited
 
 torch = pytest.importorskip("torch")
 
