@@ -88,6 +88,8 @@ def parse():
                          "the headline on the thunderstorm workload")
     ap.add_argument("--no-four-species", action="store_true",
                     help="skip the four-species entry of the default run")
+    ap.add_argument("--no-sediment", action="store_true",
+                    help="skip the sedimentation entry of the default run")
     ap.add_argument("--workload", default="thunderstorm",
                     choices=["thunderstorm", "four_species", "refined66",
                              "refined132", "refined264", "mixed"])
@@ -518,6 +520,114 @@ def run_workload(args, name, steps, warmup, cpu_seconds, with_seq):
     return ent
 
 
+def _sed_level_updates(geo, dt, nsteps):
+    """(column, species-bin, level) updates of a sedimentation call,
+    sub-steps included (the kernel's own count of sub-steps)."""
+    import numpy as np
+    c = (geo["v_cm_s"].reshape(1, 1, -1) * geo["vfac"][:, :, None] * dt /
+         geo["dz_cm"][None, :, None]).max(axis=1)       # [ncols][S*B]
+    nsub = np.maximum(np.ceil(c), 1.0)
+    return float(nsub.sum()) * nsteps * geo["nlev"]
+
+
+def run_sediment(args, steps, warmup):
+    """Sedimentation of the thunderstorm patch's 65,536 columns of 50
+    levels (the vertical term of eq. (1)), one call of the workload's 100
+    steps of 2 s per benchmark step, FP64, timed like the collision path;
+    kernel time from HIP events on the call's stream; the oracle on a
+    sample of columns on the host cores."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2409_07232_amd import _lib as L
+    from paper_2409_07232_amd import workloads as wl
+    w = wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)
+    geo = wl.sediment_geometry(w)
+    dt, nsteps = w.dt, w.nsteps
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = torch.from_numpy(w.N).to("cuda")
+    dz = torch.from_numpy(geo["dz_cm"]).to("cuda")
+    v = torch.from_numpy(geo["v_cm_s"]).to("cuda")
+    vf = torch.from_numpy(geo["vfac"]).to("cuda")
+    pr = torch.zeros((geo["ncols"], 1, w.nbins), dtype=torch.float64,
+                     device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def call():
+        h.sediment(N, geo["ncols"], geo["nlev"], geo["col_stride"],
+                   geo["lev_stride"], dz, v, vf, dt, nsteps, pr, stream=s)
+    for _ in range(warmup):
+        call()
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        call()
+    e1.record(s)
+    s.synchronize()
+    secs = time.perf_counter() - t0
+    kms = e0.elapsed_time(e1) / max(steps, 1)
+    npts = w.npoints
+    upd = _sed_level_updates(geo, dt, nsteps)
+    flops = 6.0 * upd                      # per level update: 3 mul, sub,
+    bytes_ = 16.0 * npts * w.nbins + 8.0 * npts + \
+        16.0 * geo["ncols"] * w.nbins      # (div, add); state, factors,
+    log("sedimentation %.3f ms/call" % (1e3 * secs / steps))  # precip
+    ent = {"form": "first-order upwind flux form, still air, sub-stepped "
+                   "to Courant numbers <= 1, FP64",
+           "value": round(npts * nsteps * steps / secs, 1),
+           "unit": "grid-point sedimentation updates/s",
+           "ms_per_step": round(1e3 * secs / steps, 4), "dtype": "f64",
+           "config": {"workload": "thunderstorm_patch_columns_%dx%d_%dlev_"
+                                  "33bins_liquid" % (args.nx, args.ny,
+                                                      args.nz),
+                      "columns": geo["ncols"], "levels": geo["nlev"],
+                      "dt_s": dt, "steps_per_call": nsteps,
+                      "level_updates_per_call": upd},
+           "kernel": {"name": "sed_steps<64>", "avg_call_ms": round(kms, 4)},
+           "roofline": {"bound": "alu", "achieved":
+                        round(flops / (kms * 1e-3) / 1e12, 4),
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / (kms * 1e-3) / 1e12 /
+                                      PEAK_FP64_TFLOPS, 5),
+                        "traffic": None,
+                        "flops_per_level_update": 6,
+                        "hbm_bytes_per_call_algorithmic": bytes_,
+                        "hbm_gbs_algorithmic": round(bytes_ / (kms * 1e-3)
+                                                     / 1e9, 1)}}
+    h.close()
+    if not args.no_cpu_baseline:
+        # the oracle on seeded columns, grown to about 5 s
+        rng = np.random.default_rng(12)
+        cores = oracle.max_threads()
+        ncol = 64
+        while True:
+            cols = np.sort(rng.choice(geo["ncols"], ncol, replace=False))
+            idx = cols[:, None] + np.arange(geo["nlev"])[None, :] * \
+                geo["lev_stride"]
+            sub = np.ascontiguousarray(w.N[idx]).reshape(-1, 1, w.nbins)
+            t0 = time.perf_counter()
+            oracle.sediment(sub, geo["dz_cm"], geo["v_cm_s"], dt, nsteps,
+                            vfac=geo["vfac"][cols], col_stride=geo["nlev"],
+                            lev_stride=1)
+            cs = time.perf_counter() - t0
+            if cs >= 1.5 or ncol >= geo["ncols"]:
+                break
+            ncol = min(geo["ncols"], ncol * 4)
+        ent["cpu_baseline"] = {
+            "value": round(ncol * geo["nlev"] * nsteps / cs, 1),
+            "unit": "grid-point sedimentation updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d seeded columns x %d levels x %d steps, %.1f s" % (
+                ncol, geo["nlev"], nsteps, cs)}
+    return ent
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -558,6 +668,8 @@ def main():
     if "cpu_baseline" in ent:
         line["cpu_baseline"] = ent.pop("cpu_baseline")
     line.update(ent)
+    if args.workload == "thunderstorm" and not args.no_sediment:
+        line["sedimentation"] = run_sediment(args, args.steps, args.warmup)
     if args.workload == "thunderstorm" and not args.no_four_species:
         # the second 33-bin configuration: fewer calls (each is seconds)
         fs = run_workload(args, "four_species", min(args.steps, 2), 1,

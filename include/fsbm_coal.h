@@ -205,6 +205,39 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
                          void *stream);
 
 /*
+ * Sedimentation of the handle's S x B bin spectra in vertical columns: the
+ * term d((w - V_t) f)/dz of the bin equation (Sec. III, eq. (1)) in still
+ * air (w = 0), first-order upwind in flux form, explicit.  Per (column,
+ * species-bin) each step of dt_s seconds is taken in n equal sub-steps,
+ * n = max(1, ceil(max over levels of v_l dt_s / dz_l)); per sub-step tau,
+ * with the values at its start and levels numbered from the bottom,
+ * F_l = v_l N_l tau leaves level l through its bottom face,
+ * N_l += (F_{l+1} - F_l) / dz_l (nothing enters the top level), and F_0 is
+ * added to the column's precipitation.  Number is conserved (column
+ * content plus precipitation) and N stays >= 0.
+ *  N           device, FP64, [npoints][S][B], updated in place; point
+ *              (column c, level l) is c * col_stride + l * lev_stride
+ *              (column-major grids: col_stride = nlev, lev_stride = 1;
+ *              [nz][ny][nx] grids: 1 and nx * ny).  Every addressed point
+ *              must lie in the caller's array.
+ *  ncols, nlev columns and levels, 1 <= nlev <= 64 (level 0 at the bottom)
+ *  dz_cm       device, FP64, [nlev] layer thickness (cm), > 0
+ *  v_cm_s      device, FP64, [S][B] fall speed (cm/s), >= 0
+ *  vfac        device, FP64, [ncols][nlev] factor on the fall speed at
+ *              each column and level (air-density correction), or NULL (1)
+ *  precip      device, FP64, [ncols][S][B], number per cm^2 that left the
+ *              bottom level, added to; or NULL
+ * Stream-ordered and asynchronous; ncols == 0 or nsteps == 0 is a no-op.
+ * Errors: FSBM_EINVAL (sizes, strides, dt, null pointers),
+ * FSBM_EUNSUPPORTED (nlev > 64), FSBM_EHIP.  dz_cm and v_cm_s are read on
+ * the device: values outside the ranges above give undefined results.
+ */
+int fsbm_coal_sediment(fsbm_coal_t h, double *N, int64_t ncols, int32_t nlev,
+                  int64_t col_stride, int64_t lev_stride, const double *dz_cm,
+                  const double *v_cm_s, const double *vfac, double dt_s,
+                  int32_t nsteps, double *precip, void *stream);
+
+/*
  * Explicitly autotune the kernel family and launch shape for about
  * npoints_hint cloudy points, timing candidates on synthetic states.
  * Candidates: steps per launch and waves per block (one point per lane);

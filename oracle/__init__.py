@@ -21,7 +21,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fsbm_oracle.c")
+_SRC = [os.path.join(_HERE, "fsbm_oracle.c"),
+        os.path.join(_HERE, "fsbm_oracle_sed.c")]
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
           "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
@@ -40,8 +41,8 @@ def build(force: bool = True) -> str:
     checked build ``liboracle_san.so``)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", *CFLAGS, *(SAN_FLAGS if SANITIZE else []), _SRC, "-o",
-               tmp, "-lm"]
+        cmd = ["gcc", *CFLAGS, *(SAN_FLAGS if SANITIZE else []), *_SRC,
+               "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -85,6 +86,11 @@ def _load():
             ctypes.c_double, ctypes.c_int32, dp, dp, dp, dp, lp, ip,
             ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32]
         lib.fsbm_oracle_run_gated.restype = ctypes.c_int
+        lib.fsbm_oracle_sediment.argtypes = [
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+            ctypes.c_int64, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double,
+            ctypes.c_int32, dp]
+        lib.fsbm_oracle_sediment.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
         lib.fsbm_oracle_targets.argtypes = [ctypes.POINTER(_Desc), ip, dp]
@@ -207,3 +213,39 @@ def flux_fraction(c: float, x1: float) -> float:
 
 def max_threads() -> int:
     return int(_load().fsbm_oracle_max_threads())
+
+
+def sediment(N: np.ndarray, dz_cm, v_cm_s, dt: float, nsteps: int,
+             vfac=None, col_stride=None, lev_stride=None, precip=None):
+    """Sedimentation of columns (``fsbm_oracle_sed.c``), ``N`` modified in
+    place.  N: [points][S][B] or [columns][levels][S][B] float64; levels =
+    len(dz_cm); point (column c, level l) is c * col_stride + l *
+    lev_stride (default: columns of consecutive levels).  v_cm_s: [S][B];
+    vfac: [columns][levels] or None.  Returns the precipitation per column,
+    species and bin, added to ``precip`` if given."""
+    if N.dtype != np.float64 or not N.flags.c_contiguous:
+        raise ValueError("N must be C-contiguous float64")
+    S, B = int(N.shape[-2]), int(N.shape[-1])
+    npts = int(N.size // (S * B))
+    dz = np.ascontiguousarray(dz_cm, dtype=np.float64)
+    nlev = int(dz.shape[0])
+    ncols = npts // nlev
+    if col_stride is None:
+        col_stride, lev_stride = nlev, 1
+    v = np.ascontiguousarray(v_cm_s, dtype=np.float64).reshape(S, B)
+    vf = None
+    if vfac is not None:
+        vf = np.ascontiguousarray(vfac, dtype=np.float64)
+        if vf.shape != (ncols, nlev):
+            raise ValueError("vfac must be [columns][levels]")
+    out = (np.zeros((ncols, S, B)) if precip is None else
+           np.ascontiguousarray(precip, dtype=np.float64))
+    if out.shape != (ncols, S, B):
+        raise ValueError("precip must be [columns][S][B]")
+    rc = _load().fsbm_oracle_sediment(
+        S, B, ncols, nlev, int(col_stride), int(lev_stride), _dptr(N),
+        _dptr(dz), _dptr(v), _dptr(vf) if vf is not None else None,
+        float(dt), int(nsteps), _dptr(out))
+    if rc:
+        raise ValueError("oracle rejected its input")
+    return out

@@ -96,6 +96,20 @@ double fsbm_oracle_kernel_at(const fsbm_oracle_desc *d, double p, int32_t a,
 /* Number of threads OpenMP would use. */
 int fsbm_oracle_max_threads(void);
 
+/* Sedimentation of columns: the term d((w - V_t) f)/dz of eq. (1) (Sec. III)
+ * in still air, first-order upwind in flux form, explicit, each step split
+ * into equal sub-steps with Courant numbers <= 1 (readings R18-R21, see
+ * fsbm_oracle_sed.c).  N: host [npoints][S][B], in place; point (column c,
+ * level l, level 0 at the bottom) is c * col_stride + l * lev_stride.
+ * dz_cm [nlev] > 0; v_cm_s [S][B] >= 0; vfac [ncols][nlev] or NULL;
+ * precip [ncols][S][B] or NULL, the number per cm^2 leaving the bottom level
+ * is added to it.  Returns 0, or -1 on bad input. */
+int fsbm_oracle_sediment(int32_t nspecies, int32_t nbins, int64_t ncols,
+                         int32_t nlev, int64_t col_stride,
+                         int64_t lev_stride, double *N, const double *dz_cm,
+                         const double *v_cm_s, const double *vfac,
+                         double dt, int32_t nsteps, double *precip);
+
 #ifdef __cplusplus
 }
 #endif

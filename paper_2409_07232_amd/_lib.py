@@ -35,6 +35,7 @@ FLAG_PROFILE = 8
 # every entry point declared in include/fsbm_coal.h
 EXPORTS = ("fsbm_coal_opts_default", "fsbm_coal_create", "fsbm_coal_step",
            "fsbm_coal_step_gated", "fsbm_coal_step_noalloc",
+           "fsbm_coal_sediment",
            "fsbm_coal_step_multi", "fsbm_coal_tune", "fsbm_coal_totals",
            "fsbm_coal_get_stats", "fsbm_coal_destroy", "fsbm_coal_strerror",
            "fsbm_coal_last_error")
@@ -114,6 +115,12 @@ def load(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_double, ctypes.c_int32, vp]
     lib.fsbm_coal_step_multi.restype = ctypes.c_int
+    lib.fsbm_coal_sediment.argtypes = [vp, vp, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_int64, vp, vp, vp,
+                                       ctypes.c_double, ctypes.c_int32, vp,
+                                       vp]
+    lib.fsbm_coal_sediment.restype = ctypes.c_int
     lib.fsbm_coal_tune.argtypes = [vp, ctypes.c_int64, vp]
     lib.fsbm_coal_tune.restype = ctypes.c_int
     lib.fsbm_coal_totals.argtypes = [vp, vp, vp, vp, vp]
@@ -259,6 +266,36 @@ class FsbmCoal:
         if rc != FSBM_OK:
             self._raise(rc, "fsbm_coal_step_noalloc")
         self._last_npoints = P
+
+    def sediment(self, N, ncols: int, nlev: int, col_stride: int,
+                 lev_stride: int, dz_cm, v_cm_s, vfac, dt: float,
+                 nsteps: int, precip=None, stream=None):
+        """Sedimentation of columns of N (``fsbm_coal_sediment``): dz_cm
+        [nlev], v_cm_s [S][B], vfac [ncols][nlev] or None, precip
+        [ncols][S][B] or None, all float64 device tensors."""
+        _check_state(N, self.nspecies, self.nbins)
+        P = int(N.shape[0])
+        if ncols > 0 and ((ncols - 1) * col_stride + (nlev - 1) * lev_stride
+                          >= P):
+            raise ValueError("columns reach past the state array")
+        shapes = ((dz_cm, (nlev,)), (v_cm_s, (self.nspecies, self.nbins)),
+                  (vfac, (ncols, nlev)),
+                  (precip, (ncols, self.nspecies, self.nbins)))
+        for t, shp in shapes:
+            if t is not None and (t.dtype != N.dtype or not t.is_cuda or
+                                  not t.is_contiguous() or
+                                  tuple(t.shape) != shp):
+                raise ValueError("sediment: array of shape %s expected" %
+                                 (shp,))
+        ptr = [None if t is None else t.data_ptr()
+               for t in (dz_cm, v_cm_s, vfac, precip)]
+        rc = load().fsbm_coal_sediment(self._h, N.data_ptr(), int(ncols),
+                                       int(nlev), int(col_stride),
+                                       int(lev_stride), ptr[0], ptr[1],
+                                       ptr[2], float(dt), int(nsteps), ptr[3],
+                                       _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_sediment")
 
     def totals(self):
         """Per-point (mass_before, mass_after, num_before, num_after)."""

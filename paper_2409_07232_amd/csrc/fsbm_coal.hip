@@ -1265,6 +1265,34 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
   return run_call(c, stream);
 }
 
+int fsbm_coal_sediment(fsbm_coal_t h, double *N, int64_t ncols, int32_t nlev,
+                  int64_t col_stride, int64_t lev_stride, const double *dz_cm,
+                  const double *v_cm_s, const double *vfac, double dt_s,
+                  int32_t nsteps, double *precip, void *stream) {
+  if (!h || ncols < 0 || nlev < 1 || col_stride < 0 || lev_stride < 0 ||
+      nsteps < 0 || !isfinite(dt_s) || !(dt_s > 0.0))
+    return FSBM_EINVAL;
+  if (nlev > kSedMaxLevels) return FSBM_EUNSUPPORTED;
+  if (ncols == 0 || nsteps == 0) return FSBM_OK;
+  if (!N || !dz_cm || !v_cm_s) return FSBM_EINVAL;
+  HIP_TRY(h, hipSetDevice(h->device));
+  SedArgs a{};
+  a.N = N;
+  a.ncols = ncols;
+  a.nlev = nlev;
+  a.SB = h->S * h->B;
+  a.col_stride = col_stride;
+  a.lev_stride = lev_stride;
+  a.dz = dz_cm;
+  a.v = v_cm_s;
+  a.vfac = vfac;
+  a.dt = dt_s;
+  a.nsteps = nsteps;
+  a.precip = precip;
+  HIP_TRY(h, launch_sed_steps(a, (hipStream_t)stream));
+  return FSBM_OK;
+}
+
 int fsbm_coal_tune(fsbm_coal_t h, int64_t npoints_hint, void *stream) {
   if (!h || npoints_hint < 0) return FSBM_EINVAL;
   HIP_TRY(h, hipSetDevice(h->device));

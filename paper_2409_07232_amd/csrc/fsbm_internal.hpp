@@ -193,6 +193,23 @@ struct StepArgs {
   int first_launch;     // the call's first launch
 };
 
+// Sedimentation of columns (sediment.hip): point (column c, level l) is
+// point c * col_stride + l * lev_stride of N [points][S*B].
+constexpr int kSedMaxLevels = 64;
+struct SedArgs {
+  double *N;
+  int64_t ncols;
+  int nlev;
+  int SB;
+  int64_t col_stride, lev_stride;
+  const double *dz;    // [nlev] layer thickness (cm)
+  const double *v;     // [S*B] fall speed (cm/s)
+  const double *vfac;  // [ncols][nlev] factor on the fall speed, or null
+  double dt;
+  int nsteps;
+  double *precip;      // [ncols][S*B] number per cm^2, added to; or null
+};
+
 // --- host-side launchers (defined in the kernel translation units) -------
 // nmask > 1: points are bucketed by bracket and species set (closure of
 // the species holding mass), B bins per species.
@@ -253,6 +270,9 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
 bool multi_kernel_supported(int B, int S, int s, int nbr);
 hipError_t launch_multi_step(const StepArgs &a, int max_slots,
                              hipStream_t st);
+
+// Sedimentation steps of every (column, species-bin) pair.
+hipError_t launch_sed_steps(const SedArgs &a, hipStream_t st);
 
 // One-point-per-lane kernel of the sequential (in-place) form: one species,
 // mass-doubling grid, FP64; updates the state in place (a.state).

@@ -416,3 +416,55 @@ def sample_active(w: Workload, n: int, seed: int = 0) -> np.ndarray:
         return act
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 1000 + seed))
     return np.sort(rng.choice(act, size=n, replace=False))
+
+
+# ------------------------------------------------------------ sedimentation
+def fall_speed_cm_s(x, rho, beta, vcoef=None):
+    """Fall speed [S][B] (cm/s) of every species and bin at 1000 hPa: the
+    power law v = vcoef_a r^beta_a of the collection-kernel tables (r in
+    cm; vcoef as in the multi-species tables unless given)."""
+    if vcoef is None:
+        vcoef = multi_species_vcoef(beta)
+    return np.array([vcoef[a] * radius_cm(x, rho[a]) ** beta[a]
+                     for a in range(len(rho))])
+
+
+def _species_laws(w):
+    """Densities and fall-speed exponents of a workload's species."""
+    if w.name == "four_species":
+        return RHO_4, BETA_4
+    if w.name == "seven_species_habits":
+        return RHO_7, BETA_7
+    return tuple([RHO_WATER] * w.nspecies), tuple([0.8] * w.nspecies)
+
+
+def sediment_geometry(w, nlev=None, column_major=False):
+    """Columns of a workload for sedimentation: level-major patches
+    ([nz][ny][nx], point = (level * ny + y) * nx + x) keep their grid;
+    otherwise consecutive runs of nlev points form columns.  Layers thicken
+    upward from 80 m to 140 m (1000 to 500 hPa over 50 levels spans about
+    5.5 km); fall speeds follow the kernel tables' power laws, times
+    (1000 / p)^0.4 at each point's pressure (the tables' air-density
+    factor)."""
+    shape = w.meta.get("shape") if w.meta else None
+    if shape is not None and not column_major:
+        nz, ny, nx = shape
+        nlev, ncols = nz, nx * ny
+        col_stride, lev_stride = 1, nx * ny
+    else:
+        if nlev is None:
+            raise ValueError("nlev is needed for a workload without a grid")
+        ncols = w.npoints // nlev
+        col_stride, lev_stride = nlev, 1
+    lev = np.arange(nlev)
+    dz_cm = 8000.0 + 6000.0 * lev / max(nlev - 1, 1)
+    rho, beta = _species_laws(w)
+    x = bin_masses(w.nbins, w.s, w.x1_g)
+    v = fall_speed_cm_s(x, rho, beta)
+    pts = (np.arange(ncols)[:, None] * col_stride +
+           lev[None, :] * lev_stride)
+    vfac = (1000.0 / w.p[pts]) ** 0.4
+    return {"ncols": ncols, "nlev": nlev, "col_stride": col_stride,
+            "lev_stride": lev_stride, "dz_cm": dz_cm,
+            "v_cm_s": np.ascontiguousarray(v), "vfac": np.ascontiguousarray(vfac),
+            "max_courant_per_s": float(v.max() * vfac.max() / dz_cm.min())}

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07232_amd import workloads as wl
-from tests.parity import DRIFT, check, run_oracle
+from tests.parity import DRIFT, check, expected_kernel, run_oracle
 
 torch = pytest.importorskip("torch")
 
@@ -239,6 +239,8 @@ def test_handle_reused_on_fewer_points(precision, kind):
     if kind == "lane":
         w = wl.config2(nx=8, ny=8, nz=50)
     else:
+        # four species: one point per wave (FP64) or, FP32C, one point per
+        # lane for several species
         w = wl.config3(npoints=3000)
     w.nsteps = 10
     h = L.FsbmCoal.from_workload(w, precision=precision)
@@ -249,7 +251,7 @@ def test_handle_reused_on_fewer_points(precision, kind):
     got, st, _ = run_gpu(sub, precision, handle=h)
     fresh, _, _ = run_gpu(sub, precision)
     assert np.array_equal(got, fresh)
-    assert st["kernel"] == (0 if kind == "lane" else 1)
+    assert st["kernel"] == expected_kernel(w, precision)
     ref, x, lim = run_oracle(sub)
     check(got, ref, sub.N, x, precision, "reuse-" + kind, limited=lim,
           w=sub)

@@ -1,0 +1,170 @@
+"""GPU parity of sedimentation (fsbm_coal_sediment, the vertical term of
+eq. (1)) against the FP64 oracle.  The GPU kernel performs the oracle's
+operations in the oracle's order in FP64, so the bar is bit-for-bit
+equality; conservation (column content plus precipitation) and positivity
+are checked besides."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_07232_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2409_07232_amd import _lib as L
+    return L
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _run_both(w, geo, nsteps, dt, precip0=None):
+    """(GPU state, GPU precip, oracle state, oracle precip)."""
+    L = _lib()
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    ncols, nlev, cs, ls = geo["ncols"], geo["nlev"], geo["col_stride"], \
+        geo["lev_stride"]
+    SB = w.nspecies * w.nbins
+    pr0 = np.zeros((ncols, w.nspecies, w.nbins)) if precip0 is None else \
+        precip0
+    N = _dev(w.N)
+    pr = _dev(pr0)
+    h.sediment(N, ncols, nlev, cs, ls, _dev(geo["dz_cm"]), _dev(geo["v_cm_s"]),
+               _dev(geo["vfac"]) if geo["vfac"] is not None else None, dt,
+               nsteps, pr)
+    torch.cuda.synchronize()
+    got, gpr = N.cpu().numpy(), pr.cpu().numpy()
+    h.close()
+    ref = np.array(w.N, copy=True)
+    rpr = oracle.sediment(ref, geo["dz_cm"], geo["v_cm_s"], dt, nsteps,
+                          vfac=geo["vfac"], col_stride=cs, lev_stride=ls,
+                          precip=np.array(pr0, copy=True))
+    assert SB == ref.shape[1] * ref.shape[2]
+    return got, gpr, ref, rpr
+
+
+def _conserved(w, geo, got, gpr, pr0=None):
+    dz = geo["dz_cm"]
+    nlev, ncols = geo["nlev"], geo["ncols"]
+    cs, ls = geo["col_stride"], geo["lev_stride"]
+    idx = (np.arange(ncols)[:, None] * cs + np.arange(nlev)[None, :] * ls)
+    before = np.einsum("clsb,l->csb", w.N[idx], dz)
+    after = np.einsum("clsb,l->csb", got[idx], dz) + gpr
+    if pr0 is not None:
+        after = after - pr0
+    # bins far below a column's content (spectral tails near 1e-300) lose
+    # what underflows; the bar is relative to the largest content
+    np.testing.assert_allclose(after, before, rtol=1e-12,
+                               atol=1e-13 * np.abs(before).max())
+
+
+def test_thunderstorm_patch_columns():
+    """A 16 x 16 x 50 patch, level-major ([nz][ny][nx]), 33 liquid bins,
+    fall speed 8e3 r^0.8 with the air-density factor of each level,
+    20 steps of 2 s."""
+    w = wl.config2(nx=16, ny=16, nz=50)
+    geo = wl.sediment_geometry(w)
+    got, gpr, ref, rpr = _run_both(w, geo, 20, 2.0)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gpr, rpr)
+    assert np.all(got >= 0.0)
+    assert gpr.sum() > 0.0
+    _conserved(w, geo, got, gpr)
+
+
+def test_four_species_column_major_with_substeps():
+    """Four species, column-major points, a time step long enough that the
+    fastest bins take several sub-steps; precipitation added to a nonzero
+    start."""
+    w = wl.config3(npoints=40 * 30, nsteps=1)
+    geo = wl.sediment_geometry(w, nlev=30, column_major=True)
+    rng = np.random.default_rng(2)
+    pr0 = rng.uniform(0.0, 1.0, (geo["ncols"], 4, 33))
+    got, gpr, ref, rpr = _run_both(w, geo, 7, 12.0, precip0=pr0)
+    assert geo["max_courant_per_s"] * 12.0 > 2.0
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gpr, rpr)
+    assert np.all(got >= 0.0)
+    _conserved(w, geo, got, gpr, pr0)
+
+
+@pytest.mark.parametrize("nlev", [1, 2, 31, 32, 33, 64])
+def test_level_counts_and_ragged_columns(nlev):
+    """Level counts at and around the kernel's register-array sizes, a
+    column count that leaves a partial block, no fall-speed factors."""
+    rng = np.random.default_rng(nlev)
+    ncols, B = 37, 33
+    w = wl.config2(nx=8, ny=8, nz=50)
+    N = rng.uniform(0.0, 1.0, (ncols * nlev, 1, B))
+    N[rng.random(N.shape) < 0.4] = 0.0
+    w = wl.Workload("columns", B, 1, 1, w.tables, w.p_levels, w.product,
+                    N, np.full(ncols * nlev, 800.0), 2.0, 1)
+    x = wl.bin_masses(B)
+    geo = {"ncols": ncols, "nlev": nlev, "col_stride": nlev, "lev_stride": 1,
+           "dz_cm": rng.uniform(5000.0, 20000.0, nlev),
+           "v_cm_s": wl.fall_speed_cm_s(x, (1.0,), (0.8,)),
+           "vfac": None}
+    got, gpr, ref, rpr = _run_both(w, geo, 9, 2.0)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gpr, rpr)
+    _conserved(w, geo, got, gpr)
+
+
+def test_full_size_patch_sampled_columns():
+    """The whole 256 x 256 x 50 patch in one call of 100 steps; 64 seeded
+    columns recomputed by the oracle."""
+    L = _lib()
+    w = wl.config2()
+    geo = wl.sediment_geometry(w)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    pr = torch.zeros((geo["ncols"], 1, 33), dtype=torch.float64,
+                     device="cuda")
+    h.sediment(N, geo["ncols"], geo["nlev"], geo["col_stride"],
+               geo["lev_stride"], _dev(geo["dz_cm"]), _dev(geo["v_cm_s"]),
+               _dev(geo["vfac"]), 2.0, 100, pr)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    cols = np.sort(rng.choice(geo["ncols"], 64, replace=False))
+    idx = cols[:, None] + np.arange(geo["nlev"])[None, :] * geo["lev_stride"]
+    got = N.cpu().numpy()[idx]
+    gpr = pr.cpu().numpy()[cols]
+    h.close()
+    sub = np.ascontiguousarray(w.N[idx])            # [64][nlev][1][33]
+    ref = sub.reshape(64 * geo["nlev"], 1, 33).copy()
+    rpr = oracle.sediment(ref, geo["dz_cm"], geo["v_cm_s"], 2.0, 100,
+                          vfac=geo["vfac"][cols], col_stride=geo["nlev"],
+                          lev_stride=1)
+    assert np.array_equal(got.reshape(ref.shape), ref)
+    assert np.array_equal(gpr, rpr)
+
+
+def test_argument_errors_and_no_ops():
+    L = _lib()
+    lib = L.load()
+    w = wl.config2(nx=4, ny=4, nz=10)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    dz = _dev(np.full(10, 1e4))
+    v = _dev(np.ones((1, 33)))
+    args = (N.data_ptr(), 16, 10, 1, 16, dz.data_ptr(), v.data_ptr(), None)
+    assert lib.fsbm_coal_sediment(h.handle, *args, 2.0, 0, None, None) == 0
+    assert lib.fsbm_coal_sediment(h.handle, N.data_ptr(), 0, 10, 1, 16,
+                                  dz.data_ptr(), v.data_ptr(), None, 2.0, 3,
+                                  None, None) == 0
+    assert lib.fsbm_coal_sediment(h.handle, *args, -2.0, 3, None, None) == \
+        L.FSBM_EINVAL
+    assert lib.fsbm_coal_sediment(h.handle, N.data_ptr(), 16, 65, 1, 16,
+                                  dz.data_ptr(), v.data_ptr(), None, 2.0, 3,
+                                  None, None) == L.FSBM_EUNSUPPORTED
+    assert lib.fsbm_coal_sediment(None, *args, 2.0, 3, None, None) == \
+        L.FSBM_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), w.N)
+    h.close()
