@@ -22,7 +22,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "fsbm_oracle.c"),
-        os.path.join(_HERE, "fsbm_oracle_sed.c")]
+        os.path.join(_HERE, "fsbm_oracle_sed.c"),
+        os.path.join(_HERE, "fsbm_oracle_cond.c")]
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
           "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
@@ -91,6 +92,10 @@ def _load():
             ctypes.c_int64, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double,
             ctypes.c_int32, dp]
         lib.fsbm_oracle_sediment.restype = ctypes.c_int
+        lib.fsbm_oracle_condense.argtypes = [
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int64, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp]
+        lib.fsbm_oracle_condense.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
         lib.fsbm_oracle_targets.argtypes = [ctypes.POINTER(_Desc), ip, dp]
@@ -248,4 +253,38 @@ def sediment(N: np.ndarray, dz_cm, v_cm_s, dt: float, nsteps: int,
         float(dt), int(nsteps), _dptr(out))
     if rc:
         raise ValueError("oracle rejected its input")
+    return out
+
+
+def condense(N: np.ndarray, ssat, gcoef_cm2_s, dt: float, nsteps: int,
+             s: int = 1, x1_g: float = 3.3510321638291124e-11,
+             rho: float = 1.0, evaporated=None):
+    """Condensation/evaporation (``fsbm_oracle_cond.c``) of N, modified in
+    place: N [points][B] (one spectrum per point) or [points][S][B] (species
+    0 is the one that changes).  ssat, gcoef_cm2_s: [points].  Returns the
+    evaporated mass per point (g/cm^3), added to ``evaporated`` if given."""
+    if N.dtype != np.float64 or not N.flags.c_contiguous:
+        raise ValueError("N must be C-contiguous float64")
+    if N.ndim == 3:
+        sub = np.ascontiguousarray(N[:, 0, :])
+    elif N.ndim == 2:
+        sub = N
+    else:
+        raise ValueError("N must be [points][B] or [points][S][B]")
+    P, B = int(sub.shape[0]), int(sub.shape[1])
+    sv = np.ascontiguousarray(ssat, dtype=np.float64)
+    gv = np.ascontiguousarray(gcoef_cm2_s, dtype=np.float64)
+    if sv.shape != (P,) or gv.shape != (P,):
+        raise ValueError("ssat and gcoef_cm2_s must be [points]")
+    out = (np.zeros(P) if evaporated is None else
+           np.ascontiguousarray(evaporated, dtype=np.float64))
+    if out.shape != (P,):
+        raise ValueError("evaporated must be [points]")
+    rc = _load().fsbm_oracle_condense(B, int(s), float(x1_g), float(rho), P,
+                                      _dptr(sub), _dptr(sv), _dptr(gv),
+                                      float(dt), int(nsteps), _dptr(out))
+    if rc:
+        raise ValueError("oracle rejected its input")
+    if N.ndim == 3:
+        N[:, 0, :] = sub
     return out

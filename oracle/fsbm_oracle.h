@@ -110,6 +110,17 @@ int fsbm_oracle_sediment(int32_t nspecies, int32_t nbins, int64_t ncols,
                          const double *v_cm_s, const double *vfac,
                          double dt, int32_t nsteps, double *precip);
 
+/* Condensation/evaporation of one species' spectrum at a prescribed
+ * supersaturation (fsbm_oracle_cond.c, readings R22-R25): N [npoints][nbins]
+ * updated in place over nsteps steps of dt; ssat, gcoef_cm2_s [npoints];
+ * evaporated [npoints] (g/cm^3) added to once per step, or NULL.  Grid
+ * x_k = x1 2^(k/s_grid) (exact doubling); spheres of density rho.  Returns
+ * 0, or -1 on bad input. */
+int fsbm_oracle_condense(int32_t nbins, int32_t s_grid, double x1_g,
+                         double rho_g_cm3, int64_t npoints, double *N,
+                         const double *ssat, const double *gcoef_cm2_s,
+                         double dt, int32_t nsteps, double *evaporated);
+
 #ifdef __cplusplus
 }
 #endif
