@@ -1,5 +1,6 @@
 """The oracle's pins under the address and undefined-behaviour checkers: a
-CPU build of oracle/fsbm_oracle.c with -fsanitize=address,undefined (no
+CPU build of the oracle's C sources (collision, sedimentation,
+condensation) with -fsanitize=address,undefined (no
 recovery), loaded into a Python process that preloads the checker runtime,
 runs the oracle's pin suites; any out-of-bounds access, use after free,
 leak-free misuse or undefined arithmetic aborts that process."""
@@ -39,7 +40,8 @@ def test_oracle_pins_under_address_and_ub_checkers():
     assert r.returncode == 0, r.stdout + r.stderr
     cmd = [sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu",
            "-p", "no:cacheprovider",
-           "tests/test_oracle_pins.py", "tests/test_oracle_sequential.py"]
+           "tests/test_oracle_pins.py", "tests/test_oracle_sequential.py",
+           "tests/test_oracle_sed.py", "tests/test_oracle_cond.py"]
     r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True,
                        text=True, timeout=900)
     out = r.stdout + r.stderr
