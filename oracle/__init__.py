@@ -23,7 +23,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "fsbm_oracle.c"),
         os.path.join(_HERE, "fsbm_oracle_sed.c"),
-        os.path.join(_HERE, "fsbm_oracle_cond.c")]
+        os.path.join(_HERE, "fsbm_oracle_cond.c"),
+        os.path.join(_HERE, "fsbm_oracle_break.c")]
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
           "-shared", "-fPIC", "-std=c11", "-Wall", "-Wextra"]
@@ -96,6 +97,10 @@ def _load():
             ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
             ctypes.c_int64, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp]
         lib.fsbm_oracle_condense.restype = ctypes.c_int
+        lib.fsbm_oracle_breakup.argtypes = [
+            ctypes.c_int32, ctypes.c_int64, dp, dp, dp, ctypes.c_double,
+            ctypes.c_int32]
+        lib.fsbm_oracle_breakup.restype = ctypes.c_int
         lib.fsbm_oracle_grid.argtypes = [ctypes.POINTER(_Desc), dp]
         lib.fsbm_oracle_grid.restype = ctypes.c_int
         lib.fsbm_oracle_targets.argtypes = [ctypes.POINTER(_Desc), ip, dp]
@@ -288,3 +293,29 @@ def condense(N: np.ndarray, ssat, gcoef_cm2_s, dt: float, nsteps: int,
     if N.ndim == 3:
         N[:, 0, :] = sub
     return out
+
+
+def breakup(N: np.ndarray, rate_per_s, fragments, dt: float, nsteps: int):
+    """Spontaneous breakup (``fsbm_oracle_break.c``) of N, modified in
+    place: N [points][B] or [points][S][B] (species 0 is the one that
+    changes).  rate_per_s: [B]; fragments: [B][B] (row l: fragments per
+    broken drop of bin l, zero on and above the diagonal)."""
+    if N.dtype != np.float64 or not N.flags.c_contiguous:
+        raise ValueError("N must be C-contiguous float64")
+    if N.ndim == 3:
+        sub = np.ascontiguousarray(N[:, 0, :])
+    elif N.ndim == 2:
+        sub = N
+    else:
+        raise ValueError("N must be [points][B] or [points][S][B]")
+    P, B = int(sub.shape[0]), int(sub.shape[1])
+    r = np.ascontiguousarray(rate_per_s, dtype=np.float64)
+    q = np.ascontiguousarray(fragments, dtype=np.float64)
+    if r.shape != (B,) or q.shape != (B, B):
+        raise ValueError("rate_per_s must be [B] and fragments [B][B]")
+    rc = _load().fsbm_oracle_breakup(B, P, _dptr(sub), _dptr(r), _dptr(q),
+                                     float(dt), int(nsteps))
+    if rc:
+        raise ValueError("oracle rejected its input")
+    if N.ndim == 3:
+        N[:, 0, :] = sub

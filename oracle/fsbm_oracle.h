@@ -121,6 +121,15 @@ int fsbm_oracle_condense(int32_t nbins, int32_t s_grid, double x1_g,
                          const double *ssat, const double *gcoef_cm2_s,
                          double dt, int32_t nsteps, double *evaporated);
 
+/* Spontaneous breakup of one species' spectrum (fsbm_oracle_break.c,
+ * readings R26-R28): N [npoints][nbins] updated in place over nsteps steps
+ * of dt; rate_per_s [nbins] >= 0 (bin 0's is ignored); fragments
+ * [nbins][nbins] >= 0, row l the fragments per broken drop of bin l, zero
+ * on and above the diagonal.  Returns 0, or -1 on bad input. */
+int fsbm_oracle_breakup(int32_t nbins, int64_t npoints, double *N,
+                        const double *rate_per_s, const double *fragments,
+                        double dt, int32_t nsteps);
+
 #ifdef __cplusplus
 }
 #endif

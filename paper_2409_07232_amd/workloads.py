@@ -468,3 +468,42 @@ def sediment_geometry(w, nlev=None, column_major=False):
             "lev_stride": lev_stride, "dz_cm": dz_cm,
             "v_cm_s": np.ascontiguousarray(v), "vfac": np.ascontiguousarray(vfac),
             "max_courant_per_s": float(v.max() * vfac.max() / dz_cm.min())}
+
+
+# ------------------------------------------------------------ condensation
+def condensation_inputs(w: Workload, seed: int = 0):
+    """Seeded per-point supersaturation (fraction) and growth coefficient
+    G (cm^2/s) for condensation of a workload's first species: 70 % of the
+    points growing, s ~ U[0, 1 %] (in-cloud values), 30 % evaporating,
+    |s| log-uniform in [0.1 %, 10 %] (sub-saturated air);
+    G = 1e-6 (1000 / p)^0.2 U[0.9, 1.1] (about 100 um^2/s near 10 C, rising
+    with the vapour diffusivity as the pressure falls).  Returns
+    (ssat, gcoef), float64 [npoints]."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 3000 + seed))
+    P = w.npoints
+    grow = rng.random(P) < 0.7
+    ssat = np.where(grow, rng.uniform(0.0, 0.01, P),
+                    -_log_uniform(rng, 1e-3, 0.1, P))
+    gcoef = 1e-6 * (1000.0 / w.p) ** 0.2 * rng.uniform(0.9, 1.1, P)
+    return np.ascontiguousarray(ssat), np.ascontiguousarray(gcoef)
+
+
+# ---------------------------------------------------------------- breakup
+def breakup_tables(nbins: int, s: int = 1, x1: float = X1_G,
+                   frag_ratio: float = 8.0):
+    """Spontaneous-breakup inputs of the liquid on a grid: the rate per bin,
+    P(D) = 2.94e-7 exp(34 D) s^-1 with D the drop diameter in cm (the
+    exponential form of Komabayasi, Gonda and Isono 1964; the smallest bin
+    does not break), and the fragment table: a broken drop of bin l gives
+    fragments in the bins k < l with numbers proportional to
+    exp(-x_k / xbar), xbar = x_l / frag_ratio, scaled so that their mass is
+    x_l.  Returns (rate [B], fragments [B][B])."""
+    x = bin_masses(nbins, s, x1)
+    D = 2.0 * radius_cm(x, RHO_WATER)
+    rate = 2.94e-7 * np.exp(34.0 * D)
+    rate[0] = 0.0
+    Q = np.zeros((nbins, nbins))
+    for l in range(1, nbins):
+        w = np.exp(-x[:l] / (x[l] / frag_ratio))
+        Q[l, :l] = w * (x[l] / float(w @ x[:l]))
+    return np.ascontiguousarray(rate), np.ascontiguousarray(Q)
