@@ -60,15 +60,33 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 # summary under profiles/ gives the commands).  They hold only for the
 # kernel sources they were taken on: the SHA-256 of the concatenated files
 # below must match, otherwise the traffic entry is reported as null.
-TRAFFIC_SOURCES = ("kernels_lane.hip", "device_common.hpp", "slow_path.hpp")
+LANE_SOURCES = ("kernels_lane.hip", "device_common.hpp", "slow_path.hpp")
 MEASURED_TRAFFIC = {
-    # kernel: (sources sha256, bytes per launch, profile summary)
-    "lane_step_f32c<33>": (
+    # (kernel, workload): (sources, their sha256, HBM bytes per launch,
+    # profile summary)
+    ("lane_step_f32c<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
+        LANE_SOURCES,
         "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
         4.0693e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
-    "lane_step_f64<33>": (
+    ("lane_step_f64<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
+        LANE_SOURCES,
         "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
         2.8413e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+    # the four launches (NS = 1..4) of a group of steps together
+    ("lane_multi_f32c<33,NS=1..4>", "four_species_1048576pts_33bins"): (
+        ("kernels_multi.hip", "device_common.hpp"),
+        "704bd710768e810f9cfcf96c824674f4b245dc39c46d1ddb58222107ff1137c3",
+        1.7021e10, "profiles/lane_multi_four_species_1048576x33.md"),
+    ("cond_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
+                       "prescribed_supersaturation"): (
+        ("condense.hip", "device_common.hpp"),
+        "878100426d19947a6345506058a701a8615b156fac9cb092b53bdc70c05d4db8",
+        4.096e8, "profiles/cond_brk_thunderstorm_256x256x50.md"),
+    ("brk_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
+                      "spontaneous_breakup"): (
+        ("breakup.hip", "condense.hip", "device_common.hpp"),
+        "708430229d719ca2489a2cda7f8c7a8c66c863f968c3aebb8e48cad15e1d4c98",
+        3.248e8, "profiles/cond_brk_thunderstorm_256x256x50.md"),
 }
 
 
@@ -90,6 +108,10 @@ def parse():
                     help="skip the four-species entry of the default run")
     ap.add_argument("--no-sediment", action="store_true",
                     help="skip the sedimentation entry of the default run")
+    ap.add_argument("--no-condense", action="store_true",
+                    help="skip the condensation entry of the default run")
+    ap.add_argument("--no-breakup", action="store_true",
+                    help="skip the breakup entry of the default run")
     ap.add_argument("--workload", default="thunderstorm",
                     choices=["thunderstorm", "four_species", "refined66",
                              "refined132", "refined264", "mixed"])
@@ -218,21 +240,22 @@ def measure(ws, precision, args, N0s, ps, batched=False, order=0,
     return res
 
 
-def measured_traffic(kernel):
-    """Profiled HBM bytes per launch, or None if the kernel changed."""
+def measured_traffic(kernel, workload):
+    """Profiled HBM bytes per launch of a kernel on a workload, or None if
+    there is no such record or the kernel changed since."""
     import hashlib
-    entry = MEASURED_TRAFFIC.get(kernel)
+    entry = MEASURED_TRAFFIC.get((kernel, workload))
     if entry is None:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in entry[0]:
         with open(os.path.join(ROOT, "paper_2409_07232_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
-    return entry[1] if h.hexdigest() == entry[0] else None
+    return entry[2] if h.hexdigest() == entry[1] else None
 
 
-def roofline(res, peak, kernel=None):
+def roofline(res, peak, kernel, workload):
     """The collision kernel's algorithmic rate over its profiled launches:
     pairs the fast kernel evaluated (the exact FP64 path's pairs left out)
     x FLOPS_PER_PAIR / summed launch time."""
@@ -242,7 +265,7 @@ def roofline(res, peak, kernel=None):
     all_ops = OPS_PER_PAIR_ALL * fast / secs / 1e12
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-            "traffic": measured_traffic(kernel) if kernel else None,
+            "traffic": measured_traffic(kernel, workload),
             "flops_per_pair": FLOPS_PER_PAIR,
             "ops_per_pair_incl_div_transc": OPS_PER_PAIR_ALL,
             "frac_incl_div_transc": round(all_ops / peak, 5),
@@ -475,7 +498,7 @@ def run_workload(args, name, steps, warmup, cpu_seconds, with_seq):
     ent = {"value": round(r32["updates_per_s"], 1),
            "ms_per_step": round(r32["ms_per_step"], 4),
            "config": cfg,
-           "roofline": roofline(r32, PEAK_FP32_TFLOPS, k32),
+           "roofline": roofline(r32, PEAK_FP32_TFLOPS, k32, cfg["workload"]),
            "kernel": _kernel_entry(r32, k32, nsteps, steps),
            "timing": _timing_entry(r32),
            "rates": _rates(r32, npts_all, nsteps, steps)}
@@ -484,7 +507,8 @@ def run_workload(args, name, steps, warmup, cpu_seconds, with_seq):
         ent["fp64"] = {"value": round(r64["updates_per_s"], 1),
                        "ms_per_step": round(r64["ms_per_step"], 4),
                        "dtype": "f64",
-                       "roofline": roofline(r64, PEAK_FP64_TFLOPS, k64),
+                       "roofline": roofline(r64, PEAK_FP64_TFLOPS, k64,
+                                            cfg["workload"]),
                        "kernel": _kernel_entry(r64, k64, nsteps, steps),
                        "timing": _timing_entry(r64),
                        "rates": _rates(r64, npts_all, nsteps, steps)}
@@ -495,7 +519,8 @@ def run_workload(args, name, steps, warmup, cpu_seconds, with_seq):
             "value": round(rsq["updates_per_s"], 1),
             "unit": "grid-point collision updates/s",
             "ms_per_step": round(rsq["ms_per_step"], 4), "dtype": "f64",
-            "roofline": roofline(rsq, PEAK_FP64_TFLOPS, ksq),
+            "roofline": roofline(rsq, PEAK_FP64_TFLOPS, ksq,
+                                 cfg["workload"]),
             "kernel": _kernel_entry(rsq, ksq, nsteps, steps),
             "capped_pairs": rsq["limiter_steps"],
             "timing": _timing_entry(rsq),
@@ -578,24 +603,28 @@ def run_sediment(args, steps, warmup):
     bytes_ = 16.0 * npts * w.nbins + 8.0 * npts + \
         16.0 * geo["ncols"] * w.nbins      # (div, add); state, factors,
     log("sedimentation %.3f ms/call" % (1e3 * secs / steps))  # precip
+    ent_workload = "thunderstorm_patch_columns_%dx%d_%dlev_33bins_liquid" % (
+        args.nx, args.ny, args.nz)
+    # the kernel's register array of levels
+    sed_kernel = "sed_steps<%d>" % (32 if args.nz <= 32 else
+                                    (56 if args.nz <= 56 else 64))
     ent = {"form": "first-order upwind flux form, still air, sub-stepped "
                    "to Courant numbers <= 1, FP64",
            "value": round(npts * nsteps * steps / secs, 1),
            "unit": "grid-point sedimentation updates/s",
            "ms_per_step": round(1e3 * secs / steps, 4), "dtype": "f64",
-           "config": {"workload": "thunderstorm_patch_columns_%dx%d_%dlev_"
-                                  "33bins_liquid" % (args.nx, args.ny,
-                                                      args.nz),
+           "config": {"workload": ent_workload,
                       "columns": geo["ncols"], "levels": geo["nlev"],
                       "dt_s": dt, "steps_per_call": nsteps,
                       "level_updates_per_call": upd},
-           "kernel": {"name": "sed_steps<64>", "avg_call_ms": round(kms, 4)},
+           "kernel": {"name": sed_kernel, "avg_call_ms": round(kms, 4)},
            "roofline": {"bound": "alu", "achieved":
                         round(flops / (kms * 1e-3) / 1e12, 4),
                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(flops / (kms * 1e-3) / 1e12 /
                                       PEAK_FP64_TFLOPS, 5),
-                        "traffic": None,
+                        "traffic": measured_traffic(sed_kernel,
+                                                    ent_workload),
                         "flops_per_level_update": 6,
                         "hbm_bytes_per_call_algorithmic": bytes_,
                         "hbm_gbs_algorithmic": round(bytes_ / (kms * 1e-3)
@@ -625,6 +654,193 @@ def run_sediment(args, steps, warmup):
             "kind": "oracle",
             "sample": "%d seeded columns x %d levels x %d steps, %.1f s" % (
                 ncol, geo["nlev"], nsteps, cs)}
+    return ent
+
+
+def run_condense(args, steps, warmup):
+    """Condensation/evaporation of the thunderstorm patch's drop spectra at
+    the seeded supersaturation mix (fsbm_coal_condense), one call of the
+    workload's 100 steps of 2 s per benchmark step, FP64, timed like the
+    collision path; call time from HIP events on the call's stream; the
+    oracle on a sample of cloudy points on one host core."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2409_07232_amd import _lib as L
+    from paper_2409_07232_amd import workloads as wl
+    w = wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)
+    ssat, g = wl.condensation_inputs(w)
+    dt, nsteps = w.dt, w.nsteps
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N0 = torch.from_numpy(w.N).to("cuda")
+    N = N0.clone()
+    sd = torch.from_numpy(ssat).to("cuda")
+    gd = torch.from_numpy(g).to("cuda")
+    ev = torch.zeros(w.npoints, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def call():
+        h.condense(N, sd, gd, dt, nsteps, ev, stream=s)
+    for _ in range(warmup):
+        call()
+    s.synchronize()
+    # the timed calls continue one another from the workload's state
+    N.copy_(N0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        call()
+    e1.record(s)
+    s.synchronize()
+    secs = time.perf_counter() - t0
+    kms = e0.elapsed_time(e1) / max(steps, 1)
+    act = w.cloudy() & (g * ssat != 0.0)
+    nact = int(act.sum())
+    # all 33 bins of a cloudy point hold drops (untruncated gamma spectra)
+    bins = float(np.count_nonzero(w.N[act, 0, :]))
+    flops = 12.0 * bins * nsteps
+    # state and evaporated mass of the active points read and written, s
+    # and G of every point read, the rows of the dry points scanned
+    bytes_ = 16.0 * (w.nbins + 1) * nact + 16.0 * w.npoints + \
+        8.0 * w.nbins * (w.npoints - nact)
+    h.close()
+    log("condensation %.3f ms/call" % (1e3 * secs / steps))
+    ent_workload = ("thunderstorm_patch_%dx%dx%d_33bins_liquid_prescribed_"
+                    "supersaturation" % (args.nx, args.ny, args.nz))
+    ent = {"form": "r dr/dt = G s growth, number- and mass-keeping "
+                   "remapping onto the bin grid, FP64",
+           "value": round(nact * nsteps * steps / secs, 1),
+           "unit": "grid-point condensation updates/s",
+           "ms_per_step": round(1e3 * secs / steps, 4), "dtype": "f64",
+           "config": {"workload": ent_workload,
+                      "points": w.npoints, "active_points": nact,
+                      "dt_s": dt, "steps_per_call": nsteps},
+           "kernel": {"name": "cond_steps<33>", "avg_call_ms": round(kms, 4)},
+           "roofline": {"bound": "alu", "achieved":
+                        round(flops / (kms * 1e-3) / 1e12, 4),
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / (kms * 1e-3) / 1e12 /
+                                      PEAK_FP64_TFLOPS, 5),
+                        "traffic": measured_traffic(
+                            "cond_steps<33>", ent_workload),
+                        "flops_per_bin_update": 12,
+                        "hbm_bytes_per_call_algorithmic": bytes_}}
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(13)
+        pts = np.flatnonzero(act)
+        n = 256
+        while True:
+            idx = np.sort(rng.choice(pts, min(n, pts.size), replace=False))
+            sub = np.ascontiguousarray(w.N[idx])
+            t0 = time.perf_counter()
+            oracle.condense(sub, ssat[idx], g[idx], dt, nsteps, s=w.s,
+                            x1_g=w.x1_g)
+            cs = time.perf_counter() - t0
+            if cs >= 1.5 or n >= pts.size:
+                break
+            n = min(pts.size, n * 4)
+        ent["cpu_baseline"] = {
+            "value": round(idx.size * nsteps / cs, 1),
+            "unit": "grid-point condensation updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d seeded cloudy points x %d steps, %.1f s" % (
+                idx.size, nsteps, cs)}
+    return ent
+
+
+def run_breakup(args, steps, warmup):
+    """Spontaneous breakup of the thunderstorm patch's drop spectra
+    (fsbm_coal_breakup) with the seeded rate and fragment tables, one call
+    of the workload's 100 steps of 2 s per benchmark step, FP64, timed like
+    the collision path; the oracle on a sample of cloudy points on one host
+    core."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2409_07232_amd import _lib as L
+    from paper_2409_07232_amd import workloads as wl
+    w = wl.config2(nx=args.nx, ny=args.ny, nz=args.nz)
+    rate, Q = wl.breakup_tables(w.nbins, w.s, w.x1_g)
+    dt, nsteps = w.dt, w.nsteps
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    h.set_breakup(rate, Q)
+    N0 = torch.from_numpy(w.N).to("cuda")
+    N = N0.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+
+    def call():
+        h.breakup(N, dt, nsteps, stream=s)
+    for _ in range(warmup):
+        call()
+    s.synchronize()
+    # the timed calls continue one another from the workload's state
+    N.copy_(N0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        call()
+    e1.record(s)
+    s.synchronize()
+    secs = time.perf_counter() - t0
+    kms = e0.elapsed_time(e1) / max(steps, 1)
+    h.close()
+    act = (w.N[:, 0, 1:] != 0.0).any(axis=1)
+    nact = int(act.sum())
+    B = w.nbins
+    # per point-step: B products b_l N_l, B differences, B (B - 1) / 2
+    # multiply-add pairs of the fragment sums
+    flops = float(B * B + B) * nact * nsteps
+    bytes_ = 16.0 * B * nact + 8.0 * B * (w.npoints - nact)
+    log("breakup %.3f ms/call" % (1e3 * secs / steps))
+    ent_workload = ("thunderstorm_patch_%dx%dx%d_33bins_liquid_spontaneous_"
+                    "breakup" % (args.nx, args.ny, args.nz))
+    ent = {"form": "linear spontaneous breakup, share 1 - exp(-P dt) of "
+                   "each bin per step into a fragment table, FP64",
+           "value": round(nact * nsteps * steps / secs, 1),
+           "unit": "grid-point breakup updates/s",
+           "ms_per_step": round(1e3 * secs / steps, 4), "dtype": "f64",
+           "config": {"workload": ent_workload,
+                      "points": w.npoints, "active_points": nact,
+                      "dt_s": dt, "steps_per_call": nsteps},
+           "kernel": {"name": "brk_steps<33>", "avg_call_ms": round(kms, 4)},
+           "roofline": {"bound": "alu", "achieved":
+                        round(flops / (kms * 1e-3) / 1e12, 4),
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / (kms * 1e-3) / 1e12 /
+                                      PEAK_FP64_TFLOPS, 5),
+                        "traffic": measured_traffic(
+                            "brk_steps<33>", ent_workload),
+                        "flops_per_point_step": B * B + B,
+                        "hbm_bytes_per_call_algorithmic": bytes_}}
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(14)
+        pts = np.flatnonzero(act)
+        n = 256
+        while True:
+            idx = np.sort(rng.choice(pts, min(n, pts.size), replace=False))
+            sub = np.ascontiguousarray(w.N[idx])
+            t0 = time.perf_counter()
+            oracle.breakup(sub, rate, Q, dt, nsteps)
+            cs = time.perf_counter() - t0
+            if cs >= 1.5 or n >= pts.size:
+                break
+            n = min(pts.size, n * 4)
+        ent["cpu_baseline"] = {
+            "value": round(idx.size * nsteps / cs, 1),
+            "unit": "grid-point breakup updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d seeded cloudy points x %d steps, %.1f s" % (
+                idx.size, nsteps, cs)}
     return ent
 
 
@@ -670,6 +886,10 @@ def main():
     line.update(ent)
     if args.workload == "thunderstorm" and not args.no_sediment:
         line["sedimentation"] = run_sediment(args, args.steps, args.warmup)
+    if args.workload == "thunderstorm" and not args.no_condense:
+        line["condensation"] = run_condense(args, args.steps, args.warmup)
+    if args.workload == "thunderstorm" and not args.no_breakup:
+        line["breakup"] = run_breakup(args, args.steps, args.warmup)
     if args.workload == "thunderstorm" and not args.no_four_species:
         # the second 33-bin configuration: fewer calls (each is seconds)
         fs = run_workload(args, "four_species", min(args.steps, 2), 1,

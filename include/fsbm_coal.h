@@ -238,6 +238,84 @@ int fsbm_coal_sediment(fsbm_coal_t h, double *N, int64_t ncols, int32_t nlev,
                   int32_t nsteps, double *precip, void *stream);
 
 /*
+ * Condensation and evaporation of the first species' spectrum (liquid
+ * water drops, density 1 g/cm^3) at a prescribed supersaturation: the
+ * condensation term of the bin equation (Sec. III, eq. (1)), the process
+ * the paper names as the next to offload (Sec. VIII).  Per point and step
+ * of dt_s seconds, every drop of bin k (radius r_k of the sphere of mass
+ * x_k) grows by r dr/dt = G s, i.e. r^2 -> r_k^2 + 2 G s dt_s, to the mass
+ * x' = (4 pi / 3) (r_k^2 + 2 G s dt_s)^(3/2).  Its number goes to the grid
+ * bins j, j+1 with x_j <= x' < x_{j+1} as N (1 - phi) and N phi,
+ * phi = (x' - x_j) / (x_{j+1} - x_j), which keeps number and mass;
+ * contributions are summed in ascending source bin.  Drops with
+ * r_k^2 + 2 G s dt_s <= 0 or x' < x_0 evaporate (their mass N x_k is added
+ * to evaporated); drops with x' >= x_{B-1} stay in the last bin.  Other
+ * species are not touched.  The vapour and heat budgets (the feedback on s
+ * and G) are the caller's.  The result equals this definition bit for bit
+ * (FP64, correctly rounded square root and division).
+ *  N           device, FP64, [npoints][S][B], bins of species 0 updated in
+ *              place
+ *  ssat        device, FP64, [npoints] supersaturation over water as a
+ *              fraction (s < 0 evaporates)
+ *  gcoef_cm2_s device, FP64, [npoints] growth coefficient G (cm^2/s)
+ *  evaporated  device, FP64, [npoints] evaporated mass (g/cm^3), added to
+ *              once per step; or NULL
+ * Points whose species-0 bins are all zero, or whose 2 G s dt_s is zero,
+ * are left as they are (evaporated included).  Stream-ordered and
+ * asynchronous; npoints == 0 or nsteps == 0 is a no-op.  The first call,
+ * and a call with more points than any before, allocates the handle's
+ * condensation workspace (synchronous); calls on one handle must not
+ * overlap.  Errors: FSBM_EINVAL (sizes, dt, null pointers),
+ * FSBM_EUNSUPPORTED (B other than 33 or 66, npoints >= 2^31), FSBM_ENOMEM,
+ * FSBM_EHIP.
+ */
+int fsbm_coal_condense(fsbm_coal_t h, double *N, int64_t npoints,
+                       const double *ssat, const double *gcoef_cm2_s,
+                       double dt_s, int32_t nsteps, double *evaporated,
+                       void *stream);
+
+/*
+ * Breakup tables of the first species for fsbm_coal_breakup: the breakup
+ * term of the bin equation (Sec. III, eq. (1)) in the linear form of
+ * spontaneous breakup (Srivastava 1971): a drop of bin l breaks at the rate
+ * rate_per_s[l] (s^-1) into fragments[l * B + k] drops of each smaller bin
+ * k < l; the caller balances the table's mass,
+ * sum_k fragments[l * B + k] x_k = x_l (mass is kept to that balance).
+ *  rate_per_s  host, FP64, [B], finite and >= 0; bin 0's is ignored (the
+ *              smallest drops do not break)
+ *  fragments   host, FP64, [B][B], finite and >= 0, zero for k >= l
+ * Both are copied; the caller keeps them.  The device copy is made by the
+ * next fsbm_coal_breakup.  Errors: FSBM_EINVAL (null, negative or
+ * non-finite entries, fragments on or above the diagonal),
+ * FSBM_EUNSUPPORTED (B other than 33 or 66).
+ */
+int fsbm_coal_set_breakup(fsbm_coal_t h, const double *rate_per_s,
+                          const double *fragments);
+
+/*
+ * Spontaneous breakup of the first species' spectrum with the tables of
+ * fsbm_coal_set_breakup.  Per point and step of dt_s seconds, the share
+ * b_l = 1 - exp(-P_l dt_s) of bin l's drops breaks (fragments do not break
+ * again within the step):
+ *   N'_k = (N_k - b_k N_k) + sum_{l>k} (b_l N_l) fragments[l][k],
+ * summed in ascending l.  Other species are not touched.  The result
+ * equals this definition bit for bit (FP64, b computed on the host with
+ * expm1).
+ *  N           device, FP64, [npoints][S][B], bins of species 0 updated in
+ *              place
+ * Points without drops in bins 1..B-1 are left as they are.
+ * Stream-ordered and asynchronous; npoints == 0 or nsteps == 0 is a no-op.
+ * The first call, a call with more points than any before, and a call with
+ * a dt_s other than the previous call's (or after new tables) synchronise
+ * the device and upload b and the table; calls on one handle must not
+ * overlap.  Errors: FSBM_EINVAL (sizes, dt, null N, no tables set),
+ * FSBM_EUNSUPPORTED (B other than 33 or 66, npoints >= 2^31),
+ * FSBM_ENOMEM, FSBM_EHIP.
+ */
+int fsbm_coal_breakup(fsbm_coal_t h, double *N, int64_t npoints, double dt_s,
+                      int32_t nsteps, void *stream);
+
+/*
  * Explicitly autotune the kernel family and launch shape for about
  * npoints_hint cloudy points, timing candidates on synthetic states.
  * Candidates: steps per launch and waves per block (one point per lane);

@@ -35,7 +35,8 @@ FLAG_PROFILE = 8
 # every entry point declared in include/fsbm_coal.h
 EXPORTS = ("fsbm_coal_opts_default", "fsbm_coal_create", "fsbm_coal_step",
            "fsbm_coal_step_gated", "fsbm_coal_step_noalloc",
-           "fsbm_coal_sediment",
+           "fsbm_coal_sediment", "fsbm_coal_condense",
+           "fsbm_coal_set_breakup", "fsbm_coal_breakup",
            "fsbm_coal_step_multi", "fsbm_coal_tune", "fsbm_coal_totals",
            "fsbm_coal_get_stats", "fsbm_coal_destroy", "fsbm_coal_strerror",
            "fsbm_coal_last_error")
@@ -121,6 +122,15 @@ def load(path: str = LIB_PATH):
                                        ctypes.c_double, ctypes.c_int32, vp,
                                        vp]
     lib.fsbm_coal_sediment.restype = ctypes.c_int
+    lib.fsbm_coal_condense.argtypes = [vp, vp, ctypes.c_int64, vp, vp,
+                                       ctypes.c_double, ctypes.c_int32, vp,
+                                       vp]
+    lib.fsbm_coal_condense.restype = ctypes.c_int
+    lib.fsbm_coal_set_breakup.argtypes = [vp, dp, dp]
+    lib.fsbm_coal_set_breakup.restype = ctypes.c_int
+    lib.fsbm_coal_breakup.argtypes = [vp, vp, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_int32, vp]
+    lib.fsbm_coal_breakup.restype = ctypes.c_int
     lib.fsbm_coal_tune.argtypes = [vp, ctypes.c_int64, vp]
     lib.fsbm_coal_tune.restype = ctypes.c_int
     lib.fsbm_coal_totals.argtypes = [vp, vp, vp, vp, vp]
@@ -296,6 +306,51 @@ class FsbmCoal:
                                        _stream_handle(stream))
         if rc != FSBM_OK:
             self._raise(rc, "fsbm_coal_sediment")
+
+    def condense(self, N, ssat, gcoef_cm2_s, dt: float, nsteps: int,
+                 evaporated=None, stream=None):
+        """Condensation/evaporation of species 0 (``fsbm_coal_condense``):
+        ssat and gcoef_cm2_s [npoints], evaporated [npoints] or None, all
+        float64 device tensors."""
+        _check_state(N, self.nspecies, self.nbins)
+        P = int(N.shape[0])
+        for t in (ssat, gcoef_cm2_s, evaporated):
+            if t is not None and (t.dtype != N.dtype or not t.is_cuda or
+                                  not t.is_contiguous() or
+                                  tuple(t.shape) != (P,)):
+                raise ValueError("condense: array of shape (%d,) expected" % P)
+        rc = load().fsbm_coal_condense(
+            self._h, N.data_ptr(), P, ssat.data_ptr(),
+            gcoef_cm2_s.data_ptr(), float(dt), int(nsteps),
+            None if evaporated is None else evaporated.data_ptr(),
+            _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_condense")
+
+    def set_breakup(self, rate_per_s, fragments):
+        """Breakup rates [B] and fragment table [B][B] (host arrays,
+        ``fsbm_coal_set_breakup``)."""
+        import numpy as np
+        B = self.nbins
+        r = np.ascontiguousarray(rate_per_s, dtype=np.float64)
+        q = np.ascontiguousarray(fragments, dtype=np.float64)
+        if r.shape != (B,) or q.shape != (B, B):
+            raise ValueError("rates [%d] and fragments [%d][%d] expected" %
+                             (B, B, B))
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = load().fsbm_coal_set_breakup(self._h, r.ctypes.data_as(dp),
+                                          q.ctypes.data_as(dp))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_set_breakup")
+
+    def breakup(self, N, dt: float, nsteps: int, stream=None):
+        """Spontaneous breakup of species 0 (``fsbm_coal_breakup``)."""
+        _check_state(N, self.nspecies, self.nbins)
+        rc = load().fsbm_coal_breakup(self._h, N.data_ptr(), int(N.shape[0]),
+                                      float(dt), int(nsteps),
+                                      _stream_handle(stream))
+        if rc != FSBM_OK:
+            self._raise(rc, "fsbm_coal_breakup")
 
     def totals(self):
         """Per-point (mass_before, mass_after, num_before, num_after)."""

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfsbm_coal.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["fsbm_coal.hip", "compact.hip", "kernels_lane.hip",
-           "kernels_multi.hip", "sediment.hip",
+           "kernels_multi.hip", "sediment.hip", "condense.hip",
+           "breakup.hip",
            "kernels_seq.hip", "kernels_wave.hip"]
 ARCH = "gfx950"
 

@@ -115,6 +115,17 @@ struct fsbm_coal_s {
   // the last call's workspace was a view of the scratch array (sws)
   bool last_scratch = false;
   DevWork sws{};
+  // condensation: grid masses and squared radii of the first species, the
+  // counter and index list of its compaction
+  void *cmem = nullptr;
+  int64_t ccap = -1;
+  // breakup: rates and fragment table of the first species (host copies),
+  // the step whose broken shares the device holds (< 0: none), and the
+  // device buffer [b: B][Q: B*B], counter, index list
+  std::vector<double> brk_rate, brk_Q;
+  double brk_dt = -1.0;
+  void *bmem = nullptr;
+  int64_t bcap = -1;
   // graph cache
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1265,6 +1276,174 @@ int fsbm_coal_step_multi(const fsbm_coal_t *hs, int32_t ngrids,
   return run_call(c, stream);
 }
 
+namespace {
+
+// Liquid water: x = (4 pi rho_w / 3) r^3 with rho_w = 1 g/cm^3.
+constexpr double kRhoWater = 1.0;
+double cond_vol() { return 4.0 * 3.14159265358979323846 * kRhoWater / 3.0; }
+
+size_t cond_idx_offset(int B) { return align_up(sizeof(double) * 2 * B + 4, 256); }
+
+// Condensation workspace: [x: B][r2: B] doubles, the counter, idx[cap].
+int ensure_cond(fsbm_coal_t h, int64_t npoints) {
+  if (npoints <= h->ccap) return FSBM_OK;
+  const int B = h->B;
+  const int64_t cap = std::max<int64_t>(npoints, 4096);
+  if (h->cmem) {
+    HIP_TRY(h, hipFree(h->cmem));
+    h->cmem = nullptr;
+    h->ccap = -1;
+  }
+  const size_t bytes = cond_idx_offset(B) + sizeof(int) * (size_t)cap;
+  hipError_t e = hipMalloc(&h->cmem, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->cmem = nullptr;
+    h->last_error = "condensation workspace allocation failed";
+    return FSBM_ENOMEM;
+  }
+  std::vector<double> tab(2 * (size_t)B);
+  const double vol = cond_vol();
+  for (int k = 0; k < B; ++k) {
+    const double r = cbrt(h->x[k] / vol);
+    tab[k] = h->x[k];
+    tab[B + k] = r * r;
+  }
+  HIP_TRY(h, hipMemcpy(h->cmem, tab.data(), sizeof(double) * tab.size(),
+                       hipMemcpyHostToDevice));
+  h->ccap = cap;
+  return FSBM_OK;
+}
+
+}  // namespace
+
+int fsbm_coal_condense(fsbm_coal_t h, double *N, int64_t npoints,
+                       const double *ssat, const double *gcoef_cm2_s,
+                       double dt_s, int32_t nsteps, double *evaporated,
+                       void *stream) {
+  if (!h || npoints < 0 || nsteps < 0 || !isfinite(dt_s) || !(dt_s > 0.0))
+    return FSBM_EINVAL;
+  if (!cond_supported(h->B) || npoints > 0x7fffffffLL)
+    return FSBM_EUNSUPPORTED;
+  if (npoints == 0 || nsteps == 0) return FSBM_OK;
+  if (!N || !ssat || !gcoef_cm2_s) return FSBM_EINVAL;
+  HIP_TRY(h, hipSetDevice(h->device));
+  RC_TRY(ensure_cond(h, npoints));
+  unsigned char *base = (unsigned char *)h->cmem;
+  CondArgs a{};
+  a.N = N;
+  a.npoints = npoints;
+  a.SB = h->S * h->B;
+  a.B = h->B;
+  a.s = h->s;
+  a.ssat = ssat;
+  a.gcoef = gcoef_cm2_s;
+  a.dt = dt_s;
+  a.nsteps = nsteps;
+  a.evaporated = evaporated;
+  a.x = (const double *)base;
+  a.r2 = (const double *)base + h->B;
+  a.vol = cond_vol();
+  a.count = (int *)(base + sizeof(double) * 2 * h->B);
+  a.idx = (int *)(base + cond_idx_offset(h->B));
+  HIP_TRY(h, launch_condense(a, (hipStream_t)stream));
+  return FSBM_OK;
+}
+
+namespace {
+
+size_t brk_idx_offset(int B) {
+  return align_up(sizeof(double) * ((size_t)B + (size_t)B * B) + 4, 256);
+}
+
+// Breakup workspace for npoints points; the tables are uploaded again.
+int ensure_brk(fsbm_coal_t h, int64_t npoints) {
+  if (npoints <= h->bcap) return FSBM_OK;
+  const int64_t cap = std::max<int64_t>(npoints, 4096);
+  if (h->bmem) {
+    HIP_TRY(h, hipFree(h->bmem));
+    h->bmem = nullptr;
+    h->bcap = -1;
+  }
+  const size_t bytes = brk_idx_offset(h->B) + sizeof(int) * (size_t)cap;
+  hipError_t e = hipMalloc(&h->bmem, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->bmem = nullptr;
+    h->last_error = "breakup workspace allocation failed";
+    return FSBM_ENOMEM;
+  }
+  h->bcap = cap;
+  h->brk_dt = -1.0;
+  return FSBM_OK;
+}
+
+}  // namespace
+
+int fsbm_coal_set_breakup(fsbm_coal_t h, const double *rate_per_s,
+                          const double *fragments) {
+  if (!h || !rate_per_s || !fragments) return FSBM_EINVAL;
+  if (!brk_supported(h->B)) return FSBM_EUNSUPPORTED;
+  const int B = h->B;
+  for (int l = 0; l < B; ++l) {
+    if (!(rate_per_s[l] >= 0.0) || !isfinite(rate_per_s[l]))
+      return FSBM_EINVAL;
+    for (int k = 0; k < B; ++k) {
+      const double q = fragments[(size_t)l * B + k];
+      if (!(q >= 0.0) || !isfinite(q) || (k >= l && q != 0.0))
+        return FSBM_EINVAL;
+    }
+  }
+  h->brk_rate.assign(rate_per_s, rate_per_s + B);
+  h->brk_Q.assign(fragments, fragments + (size_t)B * B);
+  h->brk_dt = -1.0;
+  return FSBM_OK;
+}
+
+int fsbm_coal_breakup(fsbm_coal_t h, double *N, int64_t npoints, double dt_s,
+                      int32_t nsteps, void *stream) {
+  if (!h || npoints < 0 || nsteps < 0 || !isfinite(dt_s) || !(dt_s > 0.0))
+    return FSBM_EINVAL;
+  if (!brk_supported(h->B) || npoints > 0x7fffffffLL)
+    return FSBM_EUNSUPPORTED;
+  if (h->brk_rate.empty()) {
+    h->last_error = "fsbm_coal_breakup: no rates and fragments set";
+    return FSBM_EINVAL;
+  }
+  if (npoints == 0 || nsteps == 0) return FSBM_OK;
+  if (!N) return FSBM_EINVAL;
+  HIP_TRY(h, hipSetDevice(h->device));
+  RC_TRY(ensure_brk(h, npoints));
+  const int B = h->B;
+  unsigned char *base = (unsigned char *)h->bmem;
+  if (dt_s != h->brk_dt) {
+    // shares broken per step: b_l = 1 - exp(-P_l dt), the smallest bin
+    // does not break; earlier calls may still read the old ones
+    std::vector<double> tab((size_t)B + (size_t)B * B);
+    tab[0] = 0.0;
+    for (int l = 1; l < B; ++l) tab[l] = -expm1(-h->brk_rate[l] * dt_s);
+    for (int l = 0; l < B; ++l)  // the kernel reads Q transposed
+      for (int k = 0; k < B; ++k)
+        tab[(size_t)B + (size_t)k * B + l] = h->brk_Q[(size_t)l * B + k];
+    HIP_TRY(h, hipDeviceSynchronize());
+    HIP_TRY(h, hipMemcpy(base, tab.data(), sizeof(double) * tab.size(),
+                         hipMemcpyHostToDevice));
+    h->brk_dt = dt_s;
+  }
+  BrkArgs a{};
+  a.N = N;
+  a.npoints = npoints;
+  a.SB = h->S * B;
+  a.B = B;
+  a.b = (const double *)base;
+  a.QT = (const double *)base + B;
+  a.nsteps = nsteps;
+  a.count = (int *)(base + sizeof(double) * ((size_t)B + (size_t)B * B));
+  a.idx = (int *)(base + brk_idx_offset(B));
+  HIP_TRY(h, launch_breakup(a, (hipStream_t)stream));
+  return FSBM_OK;
+}
+
 int fsbm_coal_sediment(fsbm_coal_t h, double *N, int64_t ncols, int32_t nlev,
                   int64_t col_stride, int64_t lev_stride, const double *dz_cm,
                   const double *v_cm_s, const double *vfac, double dt_s,
@@ -1535,6 +1714,8 @@ int fsbm_coal_destroy(fsbm_coal_t h) {
   for (auto e : h->ev_stop) hipEventDestroy(e);
   if (h->wmem) hipFree(h->wmem);
   if (h->dmem) hipFree(h->dmem);
+  if (h->cmem) hipFree(h->cmem);
+  if (h->bmem) hipFree(h->bmem);
   delete h;
   return FSBM_OK;
 }

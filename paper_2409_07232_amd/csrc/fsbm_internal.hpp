@@ -210,6 +210,23 @@ struct SedArgs {
   double *precip;      // [ncols][S*B] number per cm^2, added to; or null
 };
 
+// Condensation/evaporation of the first species' spectrum (condense.hip).
+struct CondArgs {
+  double *N;               // [npoints][S*B]; bins 0..B-1 updated
+  int64_t npoints;
+  int SB, B, s;            // row stride, bins, bins per mass doubling
+  const double *ssat;      // [npoints] supersaturation (fraction)
+  const double *gcoef;     // [npoints] growth coefficient G (cm^2/s)
+  double dt;
+  int nsteps;
+  double *evaporated;      // [npoints] g/cm^3 added to, or null
+  const double *x;         // [B] bin masses (g), device
+  const double *r2;        // [B] squared radii (cm^2), device
+  double vol;              // x = vol r^3
+  int *idx;                // [npoints] compacted points (workspace)
+  int *count;              // [1] number of compacted points (workspace)
+};
+
 // --- host-side launchers (defined in the kernel translation units) -------
 // nmask > 1: points are bucketed by bracket and species set (closure of
 // the species holding mass), B bins per species.
@@ -273,6 +290,32 @@ hipError_t launch_multi_step(const StepArgs &a, int max_slots,
 
 // Sedimentation steps of every (column, species-bin) pair.
 hipError_t launch_sed_steps(const SedArgs &a, hipStream_t st);
+
+// Compacts the points whose first species holds drops and whose growth is
+// nonzero (a.idx, a.count), then advances them a.nsteps steps.
+hipError_t launch_condense(const CondArgs &a, hipStream_t st);
+bool cond_supported(int B);  // bins per species the kernel is built for
+
+// Spontaneous breakup of the first species' spectrum (breakup.hip).
+struct BrkArgs {
+  double *N;         // [npoints][S*B]; bins 0..B-1 updated
+  int64_t npoints;
+  int SB, B;
+  const double *b;   // [B] share of a bin breaking per step, device
+  const double *QT;  // [B][B] fragments, transposed: QT[k][l] = Q[l][k]
+  int nsteps;
+  int *idx;          // [npoints] compacted points (workspace)
+  int *count;        // [1] number of compacted points (workspace)
+};
+hipError_t launch_breakup(const BrkArgs &a, hipStream_t st);
+bool brk_supported(int B);
+
+// Lists (idx, count) the points with a nonzero species-0 bin in kmin..B-1
+// and, if ssat is given, a nonzero 2 G s dt (condense.hip).
+hipError_t launch_liquid_compact(const double *N, int64_t npoints, int SB,
+                                 int B, int kmin, const double *ssat,
+                                 const double *gcoef, double dt, int *idx,
+                                 int *count, hipStream_t st);
 
 // One-point-per-lane kernel of the sequential (in-place) form: one species,
 // mass-doubling grid, FP64; updates the state in place (a.state).

@@ -1,0 +1,206 @@
+"""GPU parity of spontaneous breakup (fsbm_coal_set_breakup,
+fsbm_coal_breakup) against the FP64 oracle.  The kernel performs the
+definition's multiplications and additions in its order, unfused, with the
+broken shares computed on the host as the oracle computes them, so the bar
+is bit-for-bit equality; the other species must come back untouched."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_07232_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2409_07232_amd import _lib as L
+    return L
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _tables(w):
+    return wl.breakup_tables(w.nbins, w.s, w.x1_g)
+
+
+def _run_both(w, dt, nsteps, h=None, tables=None):
+    L = _lib()
+    rate, Q = tables if tables is not None else _tables(w)
+    own = h is None
+    if own:
+        h = L.FsbmCoal.from_workload(w, precision=0)
+        h.set_breakup(rate, Q)
+    N = _dev(w.N)
+    h.breakup(N, dt, nsteps)
+    torch.cuda.synchronize()
+    got = N.cpu().numpy()
+    if own:
+        h.close()
+    ref = np.array(w.N, copy=True)
+    oracle.breakup(ref, rate, Q, dt, nsteps)
+    return got, ref
+
+
+def _check(w, got, ref):
+    assert np.array_equal(got, ref)
+    assert np.all(got >= 0.0)
+    if w.nspecies > 1:
+        assert np.array_equal(got[:, 1:], w.N[:, 1:])
+
+
+def _broad(npoints, B, seed, nspecies=1):
+    """Spectra reaching the largest bins (so that breakup acts)."""
+    rng = np.random.default_rng(seed)
+    N = rng.uniform(0.0, 1.0, (npoints, nspecies, B)) * \
+        np.exp(-rng.uniform(0.0, 0.4, (npoints, nspecies, 1)) *
+               np.arange(B) * (33.0 / B))
+    N[rng.random(N.shape) < 0.2] = 0.0
+    return N
+
+
+def test_thunderstorm_patch():
+    """A 16 x 16 x 50 patch (15 % cloudy), 33 bins, 20 steps of 2 s."""
+    w = wl.config2(nx=16, ny=16, nz=50)
+    got, ref = _run_both(w, 2.0, 20)
+    _check(w, got, ref)
+    cl = w.cloudy()
+    assert np.array_equal(got[~cl], w.N[~cl])
+
+
+def test_broad_spectra_four_species():
+    """Four species holding drops up to the largest bins: the liquid breaks
+    (its largest bins empty), the other species are untouched."""
+    w0 = wl.config3(npoints=3000, nsteps=1)
+    w = wl.Workload("broad4", 33, 4, 1, w0.tables, w0.p_levels, w0.product,
+                    _broad(3000, 33, 5, 4), w0.p, 2.0, 1)
+    got, ref = _run_both(w, 2.0, 15)
+    _check(w, got, ref)
+    x = wl.bin_masses(33)
+    np.testing.assert_allclose(got[:, 0] @ x, w.N[:, 0] @ x, rtol=1e-13)
+    assert np.all(got[:, 0, -1] < 1e-12 * np.maximum(w.N[:, 0, -1], 1e-300))
+
+
+def test_refined_grid_66_bins():
+    """Liquid + graupel on the 66-bin grid (two bins per mass doubling)."""
+    w0 = wl.config4(nbins=66, npoints=2000, nsteps=1)
+    w = wl.Workload("broad66", 66, 2, 2, w0.tables, w0.p_levels, w0.product,
+                    _broad(2000, 66, 6, 2), w0.p, 2.0, 1)
+    got, ref = _run_both(w, 2.0, 12)
+    _check(w, got, ref)
+
+
+@pytest.mark.parametrize("npoints", [1, 63, 64, 65, 1000])
+def test_ragged_counts_and_special_points(npoints):
+    """Point counts around the 64-lane blocks; among the points: empty
+    spectra and drops in the smallest bin only (left as they are)."""
+    w0 = wl.config2(nx=4, ny=4, nz=10)
+    N = _broad(npoints, 33, npoints)
+    kinds = np.arange(npoints) % 5
+    N[kinds == 1] = 0.0
+    N[kinds == 2, 0, 1:] = 0.0
+    w = wl.Workload("ragged", 33, 1, 1, w0.tables, w0.p_levels, w0.product,
+                    N, np.full(npoints, 800.0), 2.0, 1)
+    got, ref = _run_both(w, 2.0, 4)
+    _check(w, got, ref)
+    for kind in (1, 2):
+        sel = kinds == kind
+        assert np.array_equal(got[sel], N[sel])
+
+
+def test_full_size_patch_sampled_points():
+    """The whole 256 x 256 x 50 patch (3,276,800 points) in one call of
+    100 steps of 2 s; 4096 seeded cloudy points recomputed by the oracle,
+    every dry point checked unchanged."""
+    L = _lib()
+    w = wl.config2()
+    rate, Q = _tables(w)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    h.set_breakup(rate, Q)
+    N = _dev(w.N)
+    h.breakup(N, 2.0, 100)
+    torch.cuda.synchronize()
+    got = N.cpu().numpy()
+    h.close()
+    idx = wl.sample_active(w, 4096, seed=6)
+    sub = np.ascontiguousarray(w.N[idx])
+    oracle.breakup(sub, rate, Q, 2.0, 100)
+    assert np.array_equal(got[idx], sub)
+    dry = ~w.cloudy()
+    assert np.array_equal(got[dry], w.N[dry])
+
+
+def test_new_step_and_tables_and_growing_workspace():
+    """One handle: calls with dt 2 s, then 0.5 s (the shares are uploaded
+    again), then new tables, then more points (the workspace grows); each
+    call equals the oracle's."""
+    L = _lib()
+    w0 = wl.config2(nx=4, ny=4, nz=10)
+    N = _broad(9000, 33, 11)
+    w = wl.Workload("seq", 33, 1, 1, w0.tables, w0.p_levels, w0.product,
+                    N, np.full(9000, 800.0), 2.0, 1)
+    t1 = _tables(w)
+    t2 = wl.breakup_tables(33, frag_ratio=3.0)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    try:
+        h.set_breakup(*t1)
+        for P, dt, tabs, new in ((5000, 2.0, t1, False), (300, 0.5, t1, False),
+                                 (300, 0.5, t2, True), (9000, 0.5, t2, False)):
+            if new:
+                h.set_breakup(*tabs)
+            sub = w.subset(np.arange(P))
+            got, ref = _run_both(sub, dt, 3, h=h, tables=tabs)
+            _check(sub, got, ref)
+    finally:
+        h.close()
+
+
+def test_argument_errors_and_no_ops():
+    L = _lib()
+    lib = L.load()
+    w = wl.config2(nx=4, ny=4, nz=10)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    P = w.npoints
+    # no tables yet
+    assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), P, 2.0, 3,
+                                 None) == L.FSBM_EINVAL
+    rate, Q = _tables(w)
+    for bad in ("diag", "upper", "neg"):
+        r, q = rate.copy(), Q.copy()
+        if bad == "diag":
+            q[4, 4] = 1.0
+        elif bad == "upper":
+            q[2, 7] = 1.0
+        else:
+            r[3] = -1.0
+        with pytest.raises(L.FsbmError):
+            h.set_breakup(r, q)
+    h.set_breakup(rate, Q)
+    assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), P, 2.0, 0,
+                                 None) == 0
+    assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), 0, 2.0, 3,
+                                 None) == 0
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), P, dt, 3,
+                                     None) == L.FSBM_EINVAL
+    assert lib.fsbm_coal_breakup(h.handle, None, P, 2.0, 3, None) == \
+        L.FSBM_EINVAL
+    assert lib.fsbm_coal_breakup(None, N.data_ptr(), P, 2.0, 3, None) == \
+        L.FSBM_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), w.N)
+    h.close()
+    w132 = wl.config4(nbins=132, npoints=64, nsteps=1)
+    h = L.FsbmCoal.from_workload(w132, precision=0)
+    r, q = wl.breakup_tables(132, 4)
+    with pytest.raises(L.FsbmError):
+        h.set_breakup(r, q)
+    N = _dev(w132.N)
+    assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), 64, 2.0, 3,
+                                 None) == L.FSBM_EUNSUPPORTED
+    h.close()

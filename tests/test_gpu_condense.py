@@ -1,0 +1,201 @@
+"""GPU parity of condensation/evaporation (fsbm_coal_condense) against the
+FP64 oracle.  The kernel performs the definition's operations in its order
+in FP64 (correctly rounded square root and division, the target bin found
+exactly), so the bar is bit-for-bit equality of the spectra and of the
+evaporated mass; the other species must come back untouched."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_07232_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2409_07232_amd import _lib as L
+    return L
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _run_both(w, ssat, gcoef, dt, nsteps, ev0=None, h=None):
+    """(GPU state, GPU evaporated, oracle state, oracle evaporated)."""
+    L = _lib()
+    own = h is None
+    if own:
+        h = L.FsbmCoal.from_workload(w, precision=0)
+    P = w.npoints
+    e0 = np.zeros(P) if ev0 is None else ev0
+    N = _dev(w.N)
+    ev = _dev(e0)
+    h.condense(N, _dev(ssat), _dev(gcoef), dt, nsteps, ev)
+    torch.cuda.synchronize()
+    got, gev = N.cpu().numpy(), ev.cpu().numpy()
+    if own:
+        h.close()
+    ref = np.array(w.N, copy=True)
+    rev = oracle.condense(ref, ssat, gcoef, dt, nsteps, s=w.s, x1_g=w.x1_g,
+                          rho=1.0, evaporated=np.array(e0, copy=True))
+    return got, gev, ref, rev
+
+
+def _check(w, got, gev, ref, rev):
+    assert np.array_equal(got, ref)
+    assert np.array_equal(gev, rev)
+    assert np.all(got >= 0.0)
+    if w.nspecies > 1:
+        assert np.array_equal(got[:, 1:], w.N[:, 1:])
+
+
+def test_thunderstorm_patch():
+    """A 16 x 16 x 50 patch (15 % cloudy), 33 bins, the seeded
+    supersaturation mix, 20 steps of 2 s."""
+    w = wl.config2(nx=16, ny=16, nz=50)
+    ssat, g = wl.condensation_inputs(w)
+    got, gev, ref, rev = _run_both(w, ssat, g, 2.0, 20)
+    _check(w, got, gev, ref, rev)
+    assert gev.max() > 0.0
+    cl = w.cloudy()
+    # points without drops are untouched
+    assert np.array_equal(got[~cl], w.N[~cl])
+
+
+def test_four_species_and_evaporated_start():
+    """Four species: only the liquid changes; evaporated mass is added to
+    a nonzero start."""
+    w = wl.config3(npoints=3000, nsteps=1)
+    ssat, g = wl.condensation_inputs(w, seed=1)
+    e0 = np.random.default_rng(3).uniform(0.0, 1e-6, w.npoints)
+    got, gev, ref, rev = _run_both(w, ssat, g, 2.0, 15, ev0=e0)
+    _check(w, got, gev, ref, rev)
+
+
+def test_refined_grid_66_bins():
+    """Liquid + graupel on the 66-bin grid (two bins per mass doubling)."""
+    w = wl.config4(nbins=66, npoints=2000, nsteps=1)
+    ssat, g = wl.condensation_inputs(w, seed=2)
+    got, gev, ref, rev = _run_both(w, ssat, g, 2.0, 12)
+    _check(w, got, gev, ref, rev)
+
+
+@pytest.mark.parametrize("npoints", [1, 63, 64, 65, 1000])
+def test_ragged_counts_and_special_points(npoints):
+    """Point counts around the 64-lane blocks; among the points: s = 0,
+    G = 0, empty spectra, everything evaporating in one step, growth past
+    the grid's top, drops landing exactly on a grid point."""
+    rng = np.random.default_rng(npoints)
+    B = 33
+    w0 = wl.config2(nx=4, ny=4, nz=10)
+    N = rng.uniform(0.0, 5.0, (npoints, 1, B))
+    N[rng.random(N.shape) < 0.3] = 0.0
+    x = wl.bin_masses(B)
+    r2 = np.cbrt(x / (4.0 * np.pi / 3.0)) ** 2
+    ssat = rng.uniform(-0.02, 0.02, npoints)
+    g = np.full(npoints, 1.2e-6)
+    kinds = np.arange(npoints) % 7
+    ssat[kinds == 1] = 0.0
+    g[kinds == 2] = 0.0
+    N[kinds == 3] = 0.0
+    ssat[kinds == 4] = -1.0
+    g[kinds == 4] = r2[-1]               # r^2 falls below 0 in one step
+    ssat[kinds == 5] = 1.0
+    g[kinds == 5] = 10.0 * r2[-1]        # past the top in one step
+    # bin 10 grows exactly to bin 11's mass in one step of 2 s
+    ssat[kinds == 6] = (2.0 ** (2.0 / 3.0) - 1.0) * r2[10] / (2.0 * 1e-6 * 2.0)
+    g[kinds == 6] = 1e-6
+    w = wl.Workload("ragged", B, 1, 1, w0.tables, w0.p_levels, w0.product,
+                    N, np.full(npoints, 800.0), 2.0, 1)
+    got, gev, ref, rev = _run_both(w, ssat, g, 2.0, 3)
+    _check(w, got, gev, ref, rev)
+    for kind in (1, 2, 3):
+        sel = kinds == kind
+        assert np.array_equal(got[sel], N[sel])
+        assert np.all(gev[sel] == 0.0)
+
+
+def test_full_size_patch_sampled_points():
+    """The whole 256 x 256 x 50 patch (3,276,800 points) in one call of
+    100 steps of 2 s; 4096 seeded cloudy points recomputed by the oracle,
+    every dry point checked unchanged."""
+    L = _lib()
+    w = wl.config2()
+    ssat, g = wl.condensation_inputs(w)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    ev = torch.zeros(w.npoints, dtype=torch.float64, device="cuda")
+    h.condense(N, _dev(ssat), _dev(g), 2.0, 100, ev)
+    torch.cuda.synchronize()
+    got = N.cpu().numpy()
+    gev = ev.cpu().numpy()
+    h.close()
+    idx = wl.sample_active(w, 4096, seed=5)
+    sub = np.ascontiguousarray(w.N[idx])
+    rev = oracle.condense(sub, ssat[idx], g[idx], 2.0, 100, s=w.s,
+                          x1_g=w.x1_g)
+    assert np.array_equal(got[idx], sub)
+    assert np.array_equal(gev[idx], rev)
+    dry = ~w.cloudy()
+    assert np.array_equal(got[dry], w.N[dry])
+    assert np.all(gev[dry] == 0.0)
+
+
+def test_workspace_reuse_smaller_then_larger():
+    """One handle, three calls: 5000 points, then 300, then 9000 (the
+    workspace grows); each call equals the oracle's."""
+    L = _lib()
+    w = wl.config2(nx=30, ny=30, nz=10)
+    ssat, g = wl.condensation_inputs(w, seed=4)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    try:
+        for P in (5000, 300, 9000):
+            sub = w.subset(np.arange(P))
+            got, gev, ref, rev = _run_both(sub, ssat[:P], g[:P], 2.0, 7, h=h)
+            _check(sub, got, gev, ref, rev)
+    finally:
+        h.close()
+
+
+def test_argument_errors_and_no_ops():
+    L = _lib()
+    lib = L.load()
+    w = wl.config2(nx=4, ny=4, nz=10)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    s = _dev(np.full(w.npoints, 0.01))
+    g = _dev(np.full(w.npoints, 1e-6))
+    P = w.npoints
+    assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), P, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 0, None, None) == 0
+    assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), 0, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 5, None, None) == 0
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), P,
+                                      s.data_ptr(), g.data_ptr(), dt, 5,
+                                      None, None) == L.FSBM_EINVAL
+    assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), -1, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 5, None, None) == \
+        L.FSBM_EINVAL
+    assert lib.fsbm_coal_condense(h.handle, None, P, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 5, None, None) == \
+        L.FSBM_EINVAL
+    assert lib.fsbm_coal_condense(None, N.data_ptr(), P, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 5, None, None) == \
+        L.FSBM_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(N.cpu().numpy(), w.N)
+    h.close()
+    w132 = wl.config4(nbins=132, npoints=64, nsteps=1)
+    h = L.FsbmCoal.from_workload(w132, precision=0)
+    N = _dev(w132.N)
+    s = _dev(np.full(64, 0.01))
+    g = _dev(np.full(64, 1e-6))
+    assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), 64, s.data_ptr(),
+                                  g.data_ptr(), 2.0, 5, None, None) == \
+        L.FSBM_EUNSUPPORTED
+    h.close()
