@@ -87,6 +87,10 @@ MEASURED_TRAFFIC = {
         ("breakup.hip", "condense.hip", "device_common.hpp"),
         "708430229d719ca2489a2cda7f8c7a8c66c863f968c3aebb8e48cad15e1d4c98",
         3.248e8, "profiles/cond_brk_thunderstorm_256x256x50.md"),
+    ("sed_steps<56>",
+     "thunderstorm_patch_columns_256x256_50lev_33bins_liquid"): (
+        ("sediment.hip",), "6aa1ff930411ebfb46594ceeca7f8b69034a4603fd17f9792312e0ed15b52d6d",
+        1.8175e9, "profiles/sed_steps_thunderstorm_columns_65536x50.md"),
 }
 
 

@@ -6,11 +6,13 @@
 // Mapping (gfx950): one thread per (column, species-bin) pair, consecutive
 // threads on consecutive bins of a column, so that each level of a column
 // is one contiguous run of S*B doubles read and written with consecutive
-// lane addresses.  A thread keeps its whole column (up to kSedMaxLevels
-// levels) in VGPRs for all steps of the call: the state is read once and
-// written once per call, and the sweeps in between run from registers.  The
-// kernel is bound by HBM bandwidth: 16 bytes per bin and point per call
-// (plus the per-level fall-speed factors).
+// lane addresses.  A thread keeps its whole column (register arrays of
+// 32, 56 or kSedMaxLevels levels) in VGPRs for all steps of the call: the
+// state is read once and written once per call, and the sweeps in between
+// run from registers; the layer thicknesses, the same for every thread of
+// a level, are scalar loads.  With one step per call the kernel is bound
+// by HBM bandwidth (16 bytes per bin and point, plus the fall-speed
+// factors); with many, by the FP64 division of each level update.
 //
 // Per sub-step of length tau, from the top level down, with the values at
 // the start of the sub-step: F_l = v_l N_l tau leaves level l through its
@@ -45,7 +47,7 @@ __global__ void __launch_bounds__(kSedThreads) sed_steps(SedArgs a) {
     n[l] = 0.0;
     if (l < a.nlev) {
       const double f = fac ? fac[l] : 1.0;
-      const double cl = ((v * f) * a.dt) / a.dz[l];
+      const double cl = ((v * f) * a.dt) / ldc(a.dz + l);
       cmax = cl > cmax ? cl : cmax;
       n[l] = a.N[(col * a.col_stride + (int64_t)l * a.lev_stride) * SB + q];
     }
@@ -63,7 +65,7 @@ __global__ void __launch_bounds__(kSedThreads) sed_steps(SedArgs a) {
         if (l < a.nlev) {
           const double f = fac ? fac[l] : 1.0;
           const double fout = ((v * f) * n[l]) * tau;
-          n[l] = n[l] + (fin - fout) / a.dz[l];
+          n[l] = n[l] + (fin - fout) / ldc(a.dz + l);
           fin = fout;
         }
       }
@@ -86,6 +88,9 @@ hipError_t launch_sed_steps(const SedArgs &a, hipStream_t st) {
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (a.nlev <= 32)
     hipLaunchKernelGGL(sed_steps<32>, dim3((unsigned)blocks),
+                       dim3(kSedThreads), 0, st, a);
+  else if (a.nlev <= 56)
+    hipLaunchKernelGGL(sed_steps<56>, dim3((unsigned)blocks),
                        dim3(kSedThreads), 0, st, a);
   else
     hipLaunchKernelGGL(sed_steps<kSedMaxLevels>, dim3((unsigned)blocks),

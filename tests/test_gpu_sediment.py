@@ -94,7 +94,7 @@ def test_four_species_column_major_with_substeps():
     _conserved(w, geo, got, gpr, pr0)
 
 
-@pytest.mark.parametrize("nlev", [1, 2, 31, 32, 33, 64])
+@pytest.mark.parametrize("nlev", [1, 2, 31, 32, 33, 56, 57, 64])
 def test_level_counts_and_ragged_columns(nlev):
     """Level counts at and around the kernel's register-array sizes, a
     column count that leaves a partial block, no fall-speed factors."""
