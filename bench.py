@@ -66,11 +66,11 @@ MEASURED_TRAFFIC = {
     # profile summary)
     ("lane_step_f32c<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
         LANE_SOURCES,
-        "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
-        4.0693e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+        "5ccd43de2d921f744ba141d351ea547c86a1e329cd94df008644b14e973ad29c",
+        4.1021e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
     ("lane_step_f64<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
         LANE_SOURCES,
-        "f24f844d5e2b6753c28f2791dcd4f9b540ea57e113494c416d5ee1fba78c6f5e",
+        "5ccd43de2d921f744ba141d351ea547c86a1e329cd94df008644b14e973ad29c",
         2.8413e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
     # the four launches (NS = 1..4) of a group of steps together
     ("lane_multi_f32c<33,NS=1..4>", "four_species_1048576pts_33bins"): (

@@ -7,7 +7,12 @@
  * and Sec. VI), with the collection kernels of every pair of particle types
  * tabulated at a few pressure levels and interpolated linearly for each
  * point's pressure (Sec. VI-A, "Lookup optimization"), and with the work
- * restricted to cloudy points (the predicate array of Sec. VI-B).
+ * restricted to cloudy points (the predicate array of Sec. VI-B).  The
+ * same handle also advances the other per-bin process terms of eq. (1) for
+ * its spectra: sedimentation in vertical columns (fsbm_coal_sediment), and
+ * for the first species (the drops) condensation/evaporation at a given
+ * supersaturation (fsbm_coal_condense) and spontaneous breakup
+ * (fsbm_coal_set_breakup, fsbm_coal_breakup).
  *
  * All functions return 0 on success or a negative FSBM_E* code; none aborts
  * or throws.  fsbm_coal_strerror() turns a code into text; the handle keeps

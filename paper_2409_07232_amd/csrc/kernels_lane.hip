@@ -407,12 +407,18 @@ __global__ void __launch_bounds__(kWave *WPB)
             kk[u] = in ? ldc(Kj + i0 * 2 + u) : 0.0f;
             cc[u] = in ? ldc(cj + i0 * 2 + u) : 0.0f;
           }
+          // the chunk's column masses, read from LDS together (one wait
+          // for the chunk instead of one per pair)
+          float mc[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            mc[u] = i0 + u < B - 1 ? m.get(i0 + u) : 0.0f;
 #pragma unroll
           for (int i = i0; i < i0 + 8 && i < B - 1; ++i) {
             if (!bit_of(cl, ch, i)) continue;
             const int u = 2 * (i - i0);
             const float tK = __builtin_fmaf(kk[u + 1], tjw, tj * kk[u]);
-            const float A = tK * m.get(i);
+            const float A = tK * mc[i - i0];
             // x_j / x_i = 2^(j-i) exactly on the doubling grid: the merged
             // mass A + A 2^(j-i), rounded once
             const float p2 = __builtin_bit_cast(float, (127 + j - i) << 23);
