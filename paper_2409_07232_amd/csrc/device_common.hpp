@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fp64_math.hpp"
 #include "fsbm_internal.hpp"
 
 namespace fsbm {

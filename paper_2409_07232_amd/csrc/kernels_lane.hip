@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kWave *WPB)
         const double Mtj = Mt.get(j);
         const double qj = dt * (Mtj * ldc(ixg + j));  // dt N_j, 0 if inactive
         const bool has_flux = j <= B - 2;
-        const double lnj1 = has_flux ? log(Mt.get(j + 1)) : 0.0;  // -inf if 0
+        const double lnj1 = has_flux ? log_f64(Mt.get(j + 1)) : 0.0;  // -inf if 0
         const double *Kj = Kd + (size_t)j * B * 2;  // row j: [i][2]
         const double *cj = ctab + (size_t)j * B;
         double netj = 0.0, fout = 0.0, dneg = 0.0;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kWave *WPB)
           double F = 0.0;
           if (has_flux) {
             const double den = fmax(Mtj + Sm, DBL_MIN);
-            const double x1f = fmax(lnj1 - log(den), kX1Floor);
+            const double x1f = fmax(lnj1 - log_f64(den), kX1Floor);
             F = flux_fraction_f64(ldc(cj + i), x1f) * Sm;
           }
           L.set(i, L.get(i) + A);

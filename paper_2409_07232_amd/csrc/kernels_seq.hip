@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kWave *WPB)
           bool fhit = false;
           if (j <= B - 2) {
             const double Mn = M.get(j + 1);
-            const double x1f = fmax(log(Mn / Mk), kX1Floor);
+            const double x1f = fmax(log_f64(Mn / Mk), kX1Floor);
             F = flux_fraction_f64(ldc(ci + j), x1f) * Sm;
             fhit = F > Mk;
             F = fhit ? Mk : F;

@@ -105,7 +105,7 @@ __device__ __noinline__ double entry_flux(bool has_flux, const double *Mt,
                                              double c, double Sm) {
   if (!has_flux) return 0.0;
   const double den = fmax(Mt[qt] + Sm, DBL_MIN);
-  const double x1 = fmax(lnM[qt + 1] - log(den), kX1Floor);
+  const double x1 = fmax(lnM[qt + 1] - log_f64(den), kX1Floor);
   return flux_fraction_f64(c, x1) * Sm;
 }
 
@@ -274,7 +274,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     } else {
       mass[q] = Mt;
       nv[q] = act ? no[o] : 0.0;
-      lnm[q] = log(Mt);
+      lnm[q] = log_f64(Mt);
     }
     // the pass sums of a bin with no entries stay zero (its owner writes
     // every other bin's sums in the passes)

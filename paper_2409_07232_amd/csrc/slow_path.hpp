@@ -55,7 +55,7 @@ __device__ __forceinline__ bool pair_nets_f64(const DevModel &m,
   double F = 0.0;
   if (k <= B - 2) {
     const double r = Mt[P * B + k + 1] / (Mt[P * B + k] + Sm);
-    double x1 = log(r);
+    double x1 = log_f64(r);
     if (!(x1 >= kX1Floor)) x1 = kX1Floor;
     F = flux_fraction_f64(m.ct[i * B + j], x1) * Sm;
   }
