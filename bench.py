@@ -60,37 +60,35 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 # summary under profiles/ gives the commands).  They hold only for the
 # kernel sources they were taken on: the SHA-256 of the concatenated files
 # below must match, otherwise the traffic entry is reported as null.
-LANE_SOURCES = ("kernels_lane.hip", "device_common.hpp", "slow_path.hpp")
+LANE_SOURCES = ("kernels_lane.hip", "device_common.hpp", "fp64_math.hpp",
+                "slow_path.hpp")
+_PROF_LANE = "profiles/lane_step_thunderstorm_256x256x50.md"
+_PROF_LIQ = "profiles/cond_brk_thunderstorm_256x256x50.md"
 MEASURED_TRAFFIC = {
     # (kernel, workload): (sources, their sha256, HBM bytes per launch,
     # profile summary)
     ("lane_step_f32c<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
-        LANE_SOURCES,
-        "5ccd43de2d921f744ba141d351ea547c86a1e329cd94df008644b14e973ad29c",
-        4.1021e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+        LANE_SOURCES, "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6", 4.1020e9, _PROF_LANE),
     ("lane_step_f64<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
-        LANE_SOURCES,
-        "5ccd43de2d921f744ba141d351ea547c86a1e329cd94df008644b14e973ad29c",
-        2.8413e9, "profiles/lane_step_thunderstorm_256x256x50.md"),
+        LANE_SOURCES, "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6", 2.9020e9, _PROF_LANE),
     # the four launches (NS = 1..4) of a group of steps together
     ("lane_multi_f32c<33,NS=1..4>", "four_species_1048576pts_33bins"): (
-        ("kernels_multi.hip", "device_common.hpp"),
-        "704bd710768e810f9cfcf96c824674f4b245dc39c46d1ddb58222107ff1137c3",
-        1.7021e10, "profiles/lane_multi_four_species_1048576x33.md"),
+        ("kernels_multi.hip", "device_common.hpp", "fp64_math.hpp"),
+        "7af86f1ccac6ca324a79a6f47cb61d7cbb72de42e50dcc87239980aae7c326fe", 1.7022e10,
+        "profiles/lane_multi_four_species_1048576x33.md"),
     ("cond_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
                        "prescribed_supersaturation"): (
-        ("condense.hip", "device_common.hpp"),
-        "878100426d19947a6345506058a701a8615b156fac9cb092b53bdc70c05d4db8",
-        4.096e8, "profiles/cond_brk_thunderstorm_256x256x50.md"),
+        ("condense.hip", "device_common.hpp", "fp64_math.hpp"),
+        "14d5fce9a3f6c7306492c8635b186b78a3f0a3f73a2250f5e9b7748b4172fbe6", 4.0969e8, _PROF_LIQ),
     ("brk_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
                       "spontaneous_breakup"): (
-        ("breakup.hip", "condense.hip", "device_common.hpp"),
-        "708430229d719ca2489a2cda7f8c7a8c66c863f968c3aebb8e48cad15e1d4c98",
-        3.248e8, "profiles/cond_brk_thunderstorm_256x256x50.md"),
+        ("breakup.hip", "condense.hip", "device_common.hpp",
+         "fp64_math.hpp"),
+        "8d5bd4f6450cbdc578215d71875f5d4db66aad162a546e84bf0ca178e53c9fc1", 3.2462e8, _PROF_LIQ),
     ("sed_steps<56>",
      "thunderstorm_patch_columns_256x256_50lev_33bins_liquid"): (
-        ("sediment.hip",), "6aa1ff930411ebfb46594ceeca7f8b69034a4603fd17f9792312e0ed15b52d6d",
-        1.8175e9, "profiles/sed_steps_thunderstorm_columns_65536x50.md"),
+        ("sediment.hip", "device_common.hpp", "fp64_math.hpp"), "23565fac77e596e16f2e9df62d3c97ee586c471c80af0d8eecb610409c07c3d1",
+        1.8177e9, "profiles/sed_steps_thunderstorm_columns_65536x50.md"),
 }
 
 
