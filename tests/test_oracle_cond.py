@@ -7,7 +7,8 @@ grows past it), against what the growth law and the remapping fix:
 * s = 0 is the identity, bit for bit;
 * a drop population whose growth lands exactly on a grid point moves there
   whole (the growth for a doubling of mass is (2^(2/3) - 1) r^2);
-* number is kept away from the grid's ends, and N >= 0;
+* number is kept away from the grid's ends, and N >= 0; one step moves
+  each bin's mass to exactly what the growth law gives its drops;
 * a monodisperse population converges, as the grid is refined, to the
   exact r^2 law (liquid mass N vol (r0^2 + 2 G s t)^(3/2)): a refinement
   ladder;
@@ -88,6 +89,29 @@ def test_number_kept_and_positive():
     gain = (N @ x) - (N0 @ x)
     assert np.all(np.sign(gain[ssat > 1e-4]) > 0)
     assert np.all(np.sign(gain[ssat < -1e-4]) < 0)
+
+
+def test_one_step_moves_each_bin_mass_exactly():
+    """Away from the grid's ends the remapping keeps number and mass of
+    every source bin: after one step the liquid mass is sum N_k x'_k with
+    x'_k = (4 pi / 3) (r_k^2 + 2 G s dt)^(3/2) from the growth law, and the
+    number is unchanged, both to rounding."""
+    rng = np.random.default_rng(6)
+    for s in (1, 2, 4):
+        B = 33 * s
+        x = grid(B, s)
+        r2 = np.cbrt(x / VOL) ** 2
+        N0 = np.zeros((20, B))
+        N0[:, 6 * s:20 * s] = rng.uniform(0.0, 3.0, (20, 14 * s))
+        ssat = rng.uniform(-0.003, 0.01, 20)
+        G, dt = 1.2e-6, 2.0
+        N, ev = cond(N0, ssat, G, dt, 1, s=s)
+        xnew = VOL * (r2[None, :] + 2.0 * G * ssat[:, None] * dt) ** 1.5
+        assert np.all(ev == 0.0)
+        np.testing.assert_allclose(N @ x, (N0 * xnew).sum(axis=1),
+                                   rtol=1e-13)
+        np.testing.assert_allclose(N.sum(axis=1), N0.sum(axis=1),
+                                   rtol=1e-14)
 
 
 def test_refinement_ladder_against_the_r2_law():
