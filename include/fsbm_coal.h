@@ -271,8 +271,9 @@ int fsbm_coal_sediment(fsbm_coal_t h, double *N, int64_t ncols, int32_t nlev,
  * and a call with more points than any before, allocates the handle's
  * condensation workspace (synchronous); calls on one handle must not
  * overlap.  Errors: FSBM_EINVAL (sizes, dt, null pointers),
- * FSBM_EUNSUPPORTED (B other than 33 or 66, npoints >= 2^31), FSBM_ENOMEM,
- * FSBM_EHIP.
+ * FSBM_EUNSUPPORTED (npoints >= 2^31), FSBM_ENOMEM, FSBM_EHIP.  Any grid of
+ * the library's (B <= 512 bins per species) is supported: 33 and 66 bins
+ * run one point per lane, larger grids one point per wave.
  */
 int fsbm_coal_condense(fsbm_coal_t h, double *N, int64_t npoints,
                        const double *ssat, const double *gcoef_cm2_s,
@@ -291,8 +292,8 @@ int fsbm_coal_condense(fsbm_coal_t h, double *N, int64_t npoints,
  *  fragments   host, FP64, [B][B], finite and >= 0, zero for k >= l
  * Both are copied; the caller keeps them.  The device copy is made by the
  * next fsbm_coal_breakup.  Errors: FSBM_EINVAL (null, negative or
- * non-finite entries, fragments on or above the diagonal),
- * FSBM_EUNSUPPORTED (B other than 33 or 66).
+ * non-finite entries, fragments on or above the diagonal).  Any grid of
+ * the library's (B <= 512 bins per species) is supported.
  */
 int fsbm_coal_set_breakup(fsbm_coal_t h, const double *rate_per_s,
                           const double *fragments);
@@ -314,8 +315,8 @@ int fsbm_coal_set_breakup(fsbm_coal_t h, const double *rate_per_s,
  * a dt_s other than the previous call's (or after new tables) synchronise
  * the device and upload b and the table; calls on one handle must not
  * overlap.  Errors: FSBM_EINVAL (sizes, dt, null N, no tables set),
- * FSBM_EUNSUPPORTED (B other than 33 or 66, npoints >= 2^31),
- * FSBM_ENOMEM, FSBM_EHIP.
+ * FSBM_EUNSUPPORTED (npoints >= 2^31), FSBM_ENOMEM, FSBM_EHIP.  33 and 66
+ * bins run one point per lane, larger grids one point per wave.
  */
 int fsbm_coal_breakup(fsbm_coal_t h, double *N, int64_t npoints, double dt_s,
                       int32_t nsteps, void *stream);

@@ -9,8 +9,8 @@
 // (Sec. III, eq. (1)).
 //
 // Mapping (gfx950): the points holding drops are compacted (the shared
-// liquid compaction); one point per lane, its B bins in VGPRs for all steps
-// of the call; b and the lower triangle of Q are wave-uniform and read
+// liquid compaction); at 33 and 66 bins one point per lane, its B bins in
+// VGPRs for all steps of the call; b and the lower triangle of Q are wave-uniform and read
 // through the scalar cache; every register index is static after
 // unrolling, so the step is B^2 FP64 multiply and add pairs with no memory
 // traffic.  At 66 bins the broken numbers b_l N_l are recomputed where they
@@ -79,6 +79,76 @@ __global__ void __launch_bounds__(kBrkThreads) brk_steps(BrkArgs a) {
   for (int k = 0; k < B; ++k) row[k] = n[k];
 }
 
+// Grids beyond the lane kernel (67 to kMaxBins bins): one listed point
+// per wave at a time (a grid of waves strides over the list), its bins in
+// LDS.  Lane r of the wave forms bins k = r, r + 64, ... (R of them, held
+// in registers); the rows l of the fragment table are walked in ascending
+// order by all lanes together, so the wave reads row l's entries Q[l][k]
+// for consecutive k in one access and each bin still sums its fragments in
+// ascending l, the definition's order.
+template <int R>
+__global__ void __launch_bounds__(kBrkThreads) brk_wave(BrkArgs a) {
+  extern __shared__ double lds[];
+  const int B = a.B, lane = threadIdx.x;
+  double *n = lds, *L = lds + B;
+  const int count = *a.count;
+  for (int slot = blockIdx.x; slot < count; slot += gridDim.x) {
+    const int64_t pt = a.idx[slot];
+    double *row = a.N + pt * a.SB;
+    for (int k = lane; k < B; k += kBrkThreads) n[k] = row[k];
+    __syncthreads();
+    for (int st = 0; st < a.nsteps; ++st) {
+      for (int l = lane; l < B; l += kBrkThreads) L[l] = a.b[l] * n[l];
+      __syncthreads();
+      double v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = lane + r * kBrkThreads;
+        v[r] = k < B ? n[k] - L[k] : 0.0;
+      }
+      for (int l = 1; l < B; ++l) {
+        const double Ll = L[l];
+        const double *Ql = a.Q + (size_t)l * B;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int k = lane + r * kBrkThreads;
+          if (k < l) v[r] += Ll * Ql[k];
+        }
+      }
+      __syncthreads();  // every lane has read L and n before n changes
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = lane + r * kBrkThreads;
+        if (k < B) n[k] = v[r];
+      }
+      __syncthreads();
+    }
+    for (int k = lane; k < B; k += kBrkThreads) row[k] = n[k];
+    __syncthreads();
+  }
+}
+
+template <int R>
+hipError_t launch_wave_r(const BrkArgs &a, hipStream_t st) {
+  const int64_t want = a.npoints < 2048 ? a.npoints : 2048;
+  hipLaunchKernelGGL((brk_wave<R>), dim3((unsigned)want), dim3(kBrkThreads),
+                     sizeof(double) * 2 * a.B, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave(const BrkArgs &a, hipStream_t st) {
+  switch ((a.B + kBrkThreads - 1) / kBrkThreads) {
+    case 2: return launch_wave_r<2>(a, st);
+    case 3: return launch_wave_r<3>(a, st);
+    case 4: return launch_wave_r<4>(a, st);
+    case 5: return launch_wave_r<5>(a, st);
+    case 6: return launch_wave_r<6>(a, st);
+    case 7: return launch_wave_r<7>(a, st);
+    case 8: return launch_wave_r<8>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int B, bool HOLD>
 hipError_t launch_b(const BrkArgs &a, unsigned blocks, hipStream_t st) {
   hipLaunchKernelGGL((brk_steps<B, HOLD>), dim3(blocks), dim3(kBrkThreads),
@@ -88,7 +158,9 @@ hipError_t launch_b(const BrkArgs &a, unsigned blocks, hipStream_t st) {
 
 }  // namespace
 
-bool brk_supported(int B) { return B == 33 || B == 66; }
+bool brk_supported(int B) {
+  return B == 33 || B == 66 || (B > 66 && B <= kMaxBins);
+}
 
 hipError_t launch_breakup(const BrkArgs &a, hipStream_t st) {
   if (!brk_supported(a.B) || a.npoints > 0x7fffffffLL)
@@ -98,6 +170,7 @@ hipError_t launch_breakup(const BrkArgs &a, hipStream_t st) {
   hipError_t e = launch_liquid_compact(a.N, a.npoints, a.SB, a.B, 1, nullptr,
                                        nullptr, 0.0, a.idx, a.count, st);
   if (e != hipSuccess) return e;
+  if (a.B > 66) return launch_wave(a, st);
   const unsigned blocks =
       (unsigned)((a.npoints + kBrkThreads - 1) / kBrkThreads);
   return a.B == 33 ? launch_b<33, true>(a, blocks, st)

@@ -222,6 +222,107 @@ __global__ void __launch_bounds__(kCondThreads) cond_steps(CondArgs a) {
   if (a.evaporated) a.evaporated[pt] = evap;
 }
 
+// Grids beyond the lane kernels (67 to kMaxBins bins): one listed point
+// per wave at a time (a grid of waves strides over the list), its bins in
+// LDS.  The bins' targets and weights are found once per call, one bin per
+// lane; targets rise with the source bin (-1 for evaporating sources, a
+// prefix; B - 1 for sources past the top, a suffix), so the sources that
+// bin m receives from -- targets max(m - 1, 0) and m -- are one contiguous
+// run, found by bisection.  Each step, lane r forms bins r, r + 64, ... by
+// adding its run's contributions in ascending source order, as the
+// definition adds them; the first lane sums the evaporated mass of the
+// evaporating prefix in order.
+__global__ void __launch_bounds__(kCondThreads) cond_wave(CondArgs a) {
+  extern __shared__ double lds[];
+  const int B = a.B, lane = threadIdx.x;
+  double *n = lds, *nn = lds + B, *ph = lds + 2 * B, *xs = lds + 3 * B;
+  int *tj = (int *)(lds + 4 * B);
+  int *r0 = tj + B, *r1 = r0 + B;
+  for (int k = lane; k < B; k += kCondThreads) xs[k] = a.x[k];
+  __syncthreads();
+  const double vol = a.vol, x0 = xs[0], xtop = xs[B - 1];
+  const int e0 = ilogb(x0), s = a.s;
+  const int count = *a.count;
+  for (int slot = blockIdx.x; slot < count; slot += gridDim.x) {
+    const int64_t pt = a.idx[slot];
+    double *row = a.N + pt * a.SB;
+    const double growth = 2.0 * a.gcoef[pt] * a.ssat[pt] * a.dt;
+    for (int k = lane; k < B; k += kCondThreads) {
+      n[k] = row[k];
+      double phi = 0.0;
+      int t;
+      const double rr = a.r2[k] + growth;
+      if (!(rr > 0.0)) {
+        t = -1;  // r^2 reaches zero
+      } else {
+        const double xn = vol * (rr * sqrt_rn(rr));
+        if (xn < x0) {
+          t = -1;  // below the grid
+        } else if (xn >= xtop) {
+          t = B - 1;  // past the grid's top
+        } else {
+          int j = s * (ilogb(xn) - e0 - 1);
+          j = j < 0 ? 0 : (j > B - 2 ? B - 2 : j);
+          while (j > 0 && xs[j] > xn) --j;
+          while (j < B - 2 && !(xs[j + 1] > xn)) ++j;
+          phi = (xn - xs[j]) / (xs[j + 1] - xs[j]);
+          t = j;
+        }
+      }
+      tj[k] = t;
+      ph[k] = phi;
+    }
+    __syncthreads();
+    for (int m = lane; m < B; m += kCondThreads) {
+      // first source with target >= max(m - 1, 0), first with target > m
+      const int lo_t = m > 0 ? m - 1 : 0;
+      int a0 = 0, b0 = B;
+      while (a0 < b0) {
+        const int c = (a0 + b0) >> 1;
+        if (tj[c] >= lo_t) b0 = c; else a0 = c + 1;
+      }
+      int a1 = a0, b1 = B;
+      while (a1 < b1) {
+        const int c = (a1 + b1) >> 1;
+        if (tj[c] > m) b1 = c; else a1 = c + 1;
+      }
+      r0[m] = a0;
+      r1[m] = a1;
+    }
+    int nev = 0;  // evaporating sources: the prefix with target -1
+    while (nev < B && tj[nev] < 0) ++nev;
+    double evap = a.evaporated ? a.evaporated[pt] : 0.0;
+    __syncthreads();
+    for (int st = 0; st < a.nsteps; ++st) {
+      for (int m = lane; m < B; m += kCondThreads) {
+        double acc = 0.0;
+        for (int k = r0[m]; k < r1[m]; ++k) {
+          const double nk = n[k];
+          if (nk == 0.0) continue;
+          const int t = tj[k];
+          if (t == m)
+            acc += (m == B - 1) ? nk : nk * (1.0 - ph[k]);
+          else
+            acc += nk * ph[k];
+        }
+        nn[m] = acc;
+      }
+      if (lane == 0) {
+        double ev = 0.0;
+        for (int k = 0; k < nev; ++k)
+          if (n[k] != 0.0) ev += n[k] * xs[k];
+        evap += ev;
+      }
+      __syncthreads();
+      for (int k = lane; k < B; k += kCondThreads) n[k] = nn[k];
+      __syncthreads();
+    }
+    for (int k = lane; k < B; k += kCondThreads) row[k] = n[k];
+    if (lane == 0 && a.evaporated) a.evaporated[pt] = evap;
+    __syncthreads();
+  }
+}
+
 template <int B>
 hipError_t launch_b(const CondArgs &a, unsigned blocks, hipStream_t st) {
   hipLaunchKernelGGL(cond_steps<B>, dim3(blocks), dim3(kCondThreads), 0, st,
@@ -231,7 +332,9 @@ hipError_t launch_b(const CondArgs &a, unsigned blocks, hipStream_t st) {
 
 }  // namespace
 
-bool cond_supported(int B) { return B == 33 || B == 66; }
+bool cond_supported(int B) {
+  return B == 33 || B == 66 || (B > 66 && B <= kMaxBins);
+}
 
 hipError_t launch_liquid_compact(const double *N, int64_t npoints, int SB,
                                  int B, int kmin, const double *ssat,
@@ -261,6 +364,13 @@ hipError_t launch_condense(const CondArgs &a, hipStream_t st) {
   if (e != hipSuccess) return e;
   const unsigned blocks =
       (unsigned)((a.npoints + kCondThreads - 1) / kCondThreads);
+  if (a.B > 66) {
+    const unsigned waves = (unsigned)(a.npoints < 2048 ? a.npoints : 2048);
+    const size_t lds = (sizeof(double) * 4 + sizeof(int) * 3) * (size_t)a.B;
+    hipLaunchKernelGGL(cond_wave, dim3(waves), dim3(kCondThreads), lds, st,
+                       a);
+    return hipGetLastError();
+  }
   return a.B == 33 ? launch_b<33>(a, blocks, st) : launch_b<66>(a, blocks, st);
 }
 

@@ -1352,8 +1352,10 @@ int fsbm_coal_condense(fsbm_coal_t h, double *N, int64_t npoints,
 
 namespace {
 
+// [b: B][QT: B*B][Q: B*B] doubles, the counter, the index list
+size_t brk_tab_doubles(int B) { return (size_t)B + 2 * (size_t)B * B; }
 size_t brk_idx_offset(int B) {
-  return align_up(sizeof(double) * ((size_t)B + (size_t)B * B) + 4, 256);
+  return align_up(sizeof(double) * brk_tab_doubles(B) + 4, 256);
 }
 
 // Breakup workspace for npoints points; the tables are uploaded again.
@@ -1419,12 +1421,16 @@ int fsbm_coal_breakup(fsbm_coal_t h, double *N, int64_t npoints, double dt_s,
   if (dt_s != h->brk_dt) {
     // shares broken per step: b_l = 1 - exp(-P_l dt), the smallest bin
     // does not break; earlier calls may still read the old ones
-    std::vector<double> tab((size_t)B + (size_t)B * B);
+    std::vector<double> tab(brk_tab_doubles(B));
     tab[0] = 0.0;
     for (int l = 1; l < B; ++l) tab[l] = -expm1(-h->brk_rate[l] * dt_s);
-    for (int l = 0; l < B; ++l)  // the kernel reads Q transposed
-      for (int k = 0; k < B; ++k)
+    // the lane kernels read Q transposed, the wave kernel as given
+    for (int l = 0; l < B; ++l)
+      for (int k = 0; k < B; ++k) {
         tab[(size_t)B + (size_t)k * B + l] = h->brk_Q[(size_t)l * B + k];
+        tab[(size_t)B + (size_t)B * B + (size_t)l * B + k] =
+            h->brk_Q[(size_t)l * B + k];
+      }
     HIP_TRY(h, hipDeviceSynchronize());
     HIP_TRY(h, hipMemcpy(base, tab.data(), sizeof(double) * tab.size(),
                          hipMemcpyHostToDevice));
@@ -1437,8 +1443,9 @@ int fsbm_coal_breakup(fsbm_coal_t h, double *N, int64_t npoints, double dt_s,
   a.B = B;
   a.b = (const double *)base;
   a.QT = (const double *)base + B;
+  a.Q = a.QT + (size_t)B * B;
   a.nsteps = nsteps;
-  a.count = (int *)(base + sizeof(double) * ((size_t)B + (size_t)B * B));
+  a.count = (int *)(base + sizeof(double) * brk_tab_doubles(B));
   a.idx = (int *)(base + brk_idx_offset(B));
   HIP_TRY(h, launch_breakup(a, (hipStream_t)stream));
   return FSBM_OK;

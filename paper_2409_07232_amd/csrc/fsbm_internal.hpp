@@ -303,6 +303,7 @@ struct BrkArgs {
   int SB, B;
   const double *b;   // [B] share of a bin breaking per step, device
   const double *QT;  // [B][B] fragments, transposed: QT[k][l] = Q[l][k]
+  const double *Q;   // [B][B] fragments, Q[l][k] (wave kernel)
   int nsteps;
   int *idx;          // [npoints] compacted points (workspace)
   int *count;        // [1] number of compacted points (workspace)

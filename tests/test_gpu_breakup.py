@@ -195,12 +195,39 @@ def test_argument_errors_and_no_ops():
     torch.cuda.synchronize()
     assert np.array_equal(N.cpu().numpy(), w.N)
     h.close()
-    w132 = wl.config4(nbins=132, npoints=64, nsteps=1)
-    h = L.FsbmCoal.from_workload(w132, precision=0)
-    r, q = wl.breakup_tables(132, 4)
-    with pytest.raises(L.FsbmError):
-        h.set_breakup(r, q)
-    N = _dev(w132.N)
-    assert lib.fsbm_coal_breakup(h.handle, N.data_ptr(), 64, 2.0, 3,
-                                 None) == L.FSBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("nbins,s,npts", [(132, 4, 700), (264, 8, 300),
+                                          (512, 16, 65)])
+def test_refined_grids_one_point_per_wave(nbins, s, npts):
+    """Grids beyond the lane kernels (one point per wave): 132, 264 and the
+    largest, 512 bins, point counts that leave the wave grid ragged."""
+    N = _broad(npts, nbins, nbins, 1)
+    w = wl.Workload("broad%d" % nbins, nbins, 1, s,
+                    wl.liquid_tables(nbins, s), wl.P_LEVELS_3.copy(),
+                    np.zeros((1, 1), np.int32), N, np.full(npts, 800.0),
+                    2.0, 1)
+    got, ref = _run_both(w, 2.0, 6)
+    _check(w, got, ref)
+    x = wl.bin_masses(nbins, s)
+    np.testing.assert_allclose(got[:, 0] @ x, N[:, 0] @ x, rtol=1e-12)
+
+
+def test_full_size_264_bins_sampled_points():
+    """Liquid + graupel on the 264-bin grid, 262,144 points, one call of
+    100 steps of 2 s; 256 seeded points recomputed by the oracle."""
+    L = _lib()
+    w0 = wl.config4(nbins=264)
+    rate, Q = _tables(w0)
+    h = L.FsbmCoal.from_workload(w0, precision=0)
+    h.set_breakup(rate, Q)
+    N = _dev(w0.N)
+    h.breakup(N, 2.0, 100)
+    torch.cuda.synchronize()
+    got = N.cpu().numpy()
     h.close()
+    idx = wl.sample_active(w0, 256, seed=7)
+    sub = np.ascontiguousarray(w0.N[idx])
+    oracle.breakup(sub, rate, Q, 2.0, 100)
+    assert np.array_equal(got[idx], sub)
+    assert np.array_equal(got[:, 1:], w0.N[:, 1:])

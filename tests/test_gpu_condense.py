@@ -190,12 +190,55 @@ def test_argument_errors_and_no_ops():
     torch.cuda.synchronize()
     assert np.array_equal(N.cpu().numpy(), w.N)
     h.close()
-    w132 = wl.config4(nbins=132, npoints=64, nsteps=1)
-    h = L.FsbmCoal.from_workload(w132, precision=0)
-    N = _dev(w132.N)
-    s = _dev(np.full(64, 0.01))
-    g = _dev(np.full(64, 1e-6))
-    assert lib.fsbm_coal_condense(h.handle, N.data_ptr(), 64, s.data_ptr(),
-                                  g.data_ptr(), 2.0, 5, None, None) == \
-        L.FSBM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("nbins,s,npts", [(132, 4, 700), (264, 8, 300),
+                                          (512, 16, 65)])
+def test_refined_grids_one_point_per_wave(nbins, s, npts):
+    """Grids beyond the lane kernels (one point per wave): 132, 264 and the
+    largest, 512 bins; growing and evaporating points, some past either end
+    of the grid in one step."""
+    rng = np.random.default_rng(nbins)
+    N = rng.uniform(0.0, 1.0, (npts, 1, nbins)) * np.exp(
+        -rng.uniform(0.0, 0.4, (npts, 1, 1)) * np.arange(nbins) / s)
+    N[rng.random(N.shape) < 0.2] = 0.0
+    w = wl.Workload("refined%d" % nbins, nbins, 1, s,
+                    wl.liquid_tables(nbins, s), wl.P_LEVELS_3.copy(),
+                    np.zeros((1, 1), np.int32), N, np.full(npts, 800.0),
+                    2.0, 1)
+    ssat = np.where(rng.random(npts) < 0.6, rng.uniform(0.0, 0.02, npts),
+                    -rng.uniform(0.001, 0.2, npts))
+    g = rng.uniform(0.8e-6, 1.2e-6, npts)
+    x = wl.bin_masses(nbins, s)
+    r2 = np.cbrt(x / (4.0 * np.pi / 3.0)) ** 2
+    g[::11] = 10.0 * r2[-1]        # past the top in one step
+    ssat[::11] = 1.0
+    g[5::11] = r2[-1]              # everything evaporates in one step
+    ssat[5::11] = -1.0
+    got, gev, ref, rev = _run_both(w, ssat, g, 2.0, 6)
+    _check(w, got, gev, ref, rev)
+    assert gev.max() > 0.0
+
+
+def test_full_size_264_bins_sampled_points():
+    """Liquid + graupel on the 264-bin grid, 262,144 points, one call of
+    100 steps of 2 s with the seeded supersaturation mix; 256 seeded points
+    recomputed by the oracle, graupel untouched."""
+    L = _lib()
+    w = wl.config4(nbins=264)
+    ssat, g = wl.condensation_inputs(w, seed=3)
+    h = L.FsbmCoal.from_workload(w, precision=0)
+    N = _dev(w.N)
+    ev = torch.zeros(w.npoints, dtype=torch.float64, device="cuda")
+    h.condense(N, _dev(ssat), _dev(g), 2.0, 100, ev)
+    torch.cuda.synchronize()
+    got = N.cpu().numpy()
+    gev = ev.cpu().numpy()
     h.close()
+    idx = wl.sample_active(w, 256, seed=8)
+    sub = np.ascontiguousarray(w.N[idx])
+    rev = oracle.condense(sub, ssat[idx], g[idx], 2.0, 100, s=w.s,
+                          x1_g=w.x1_g)
+    assert np.array_equal(got[idx], sub)
+    assert np.array_equal(gev[idx], rev)
+    assert np.array_equal(got[:, 1:], w.N[:, 1:])
