@@ -68,26 +68,34 @@ MEASURED_TRAFFIC = {
     # (kernel, workload): (sources, their sha256, HBM bytes per launch,
     # profile summary)
     ("lane_step_f32c<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
-        LANE_SOURCES, "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6", 4.1020e9, _PROF_LANE),
+        LANE_SOURCES,
+        "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6",
+        4.1020e9, _PROF_LANE),
     ("lane_step_f64<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
-        LANE_SOURCES, "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6", 2.9020e9, _PROF_LANE),
+        LANE_SOURCES,
+        "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6",
+        2.9020e9, _PROF_LANE),
     # the four launches (NS = 1..4) of a group of steps together
     ("lane_multi_f32c<33,NS=1..4>", "four_species_1048576pts_33bins"): (
         ("kernels_multi.hip", "device_common.hpp", "fp64_math.hpp"),
-        "7af86f1ccac6ca324a79a6f47cb61d7cbb72de42e50dcc87239980aae7c326fe", 1.7022e10,
+        "7af86f1ccac6ca324a79a6f47cb61d7cbb72de42e50dcc87239980aae7c326fe",
+        1.7022e10,
         "profiles/lane_multi_four_species_1048576x33.md"),
     ("cond_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
                        "prescribed_supersaturation"): (
         ("condense.hip", "device_common.hpp", "fp64_math.hpp"),
-        "14d5fce9a3f6c7306492c8635b186b78a3f0a3f73a2250f5e9b7748b4172fbe6", 4.0969e8, _PROF_LIQ),
+        "88378ab700895a482b5cf270ba2fd0056e0e5f61f2a23c8a4a6290a20f7d4518",
+        4.0955e8, _PROF_LIQ),
     ("brk_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
                       "spontaneous_breakup"): (
         ("breakup.hip", "condense.hip", "device_common.hpp",
          "fp64_math.hpp"),
-        "8d5bd4f6450cbdc578215d71875f5d4db66aad162a546e84bf0ca178e53c9fc1", 3.2462e8, _PROF_LIQ),
+        "838efcfb004611665b84befbef40e45b5ffc80ad4c8e9303b00fd9ef1bb45a17",
+        3.2392e8, _PROF_LIQ),
     ("sed_steps<56>",
      "thunderstorm_patch_columns_256x256_50lev_33bins_liquid"): (
-        ("sediment.hip", "device_common.hpp", "fp64_math.hpp"), "23565fac77e596e16f2e9df62d3c97ee586c471c80af0d8eecb610409c07c3d1",
+        ("sediment.hip", "device_common.hpp", "fp64_math.hpp"),
+        "23565fac77e596e16f2e9df62d3c97ee586c471c80af0d8eecb610409c07c3d1",
         1.8177e9, "profiles/sed_steps_thunderstorm_columns_65536x50.md"),
 }
 
