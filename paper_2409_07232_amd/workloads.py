@@ -273,6 +273,38 @@ def config3(npoints: int = 1 << 20, nsteps: int = 100,
                     meta={"species": SPECIES_4})
 
 
+# The first four-species recipe: a liquid + crystal collision makes graupel,
+# and every species carries the cloud-drop spectrum, all falling at the
+# drop's speed at 100 um (smaller ice particles fall faster than drops of
+# their radius).  Crystals collect droplets fast enough to over-demand
+# their bins, so the positivity limiter fires at most points: the recipe
+# exercises the limiter, the bench's four-species workload the method.
+PRODUCT_4_GRAUPEL = np.array([[0, 3, 2, 3],
+                              [3, 2, 2, 3],
+                              [2, 2, 2, 3],
+                              [3, 3, 3, 3]], dtype=np.int32)
+
+
+def config3_limiter_heavy(npoints: int = 1 << 20, nsteps: int = 100,
+                          dt: float = 2.0) -> Workload:
+    """Config 3's species, kernels' construction, presence draws and active
+    windows with the first recipe above (seed 8)."""
+    rng = rng_for(8)
+    B, S = 33, 4
+    x = bin_masses(B)
+    present = np.ones((npoints, S), dtype=bool)
+    present[:, 1:] = rng.random((npoints, 3)) < 0.3
+    N = _multi_species_states(rng, x, RHO_4, (RBAR_4[0],) * S,
+                              (CONTENT_4[0],) * S, present, npoints,
+                              ((0, 5), (15, 32)))
+    p = rng.uniform(500.0, 1000.0, npoints)
+    vcoef = tuple(8.0e3 * 100.0e-4 ** (0.8 - b) for b in BETA_4)
+    tables = gravitational_tables(B, 1, RHO_4, BETA_4, vcoef, P_LEVELS_3)
+    return Workload("four_species_limiter_heavy", B, S, 1, tables,
+                    P_LEVELS_3.copy(), PRODUCT_4_GRAUPEL.copy(), N, p, dt,
+                    nsteps, meta={"species": SPECIES_4})
+
+
 # ------------------------------------------------- ice-crystal habits
 # FSBM keeps the ice-crystal spectrum per habit (a second dimension of the
 # crystal arrays, Sec. VI-C); here three habits (columns, plates,

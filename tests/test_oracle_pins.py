@@ -279,6 +279,17 @@ def test_laws_four_species_subset():
     _check_laws(wl.config3(npoints=512), 8, 20)
 
 
+def test_laws_four_species_limiter_heavy():
+    """The first four-species recipe: the limiter fires at most points and
+    the laws hold at every step all the same."""
+    w = wl.config3_limiter_heavy(npoints=256, nsteps=20)
+    om = model_of(w)
+    N = w.N.copy()
+    r = om.run(N, w.p, w.dt, w.nsteps)
+    assert (r["limiter_per_point"] > 0).mean() > 0.5
+    _check_laws(w, 16, 20)
+
+
 def test_laws_seven_species_habits_subset():
     _check_laws(wl.config_habits(npoints=512), 8, 20)
 
