@@ -100,7 +100,10 @@ __device__ __forceinline__ void entry_amounts(float K, float tau, float na,
 
 // Flux that a pair with merged mass Sm landing in bin qt moves on to qt+1;
 // the gain and the loss side call the same function with the same inputs.
-__device__ __noinline__ double entry_flux(bool has_flux, const double *Mt,
+// Inlined: as a call it needs every load in flight to land first (the
+// batch's operand loads of the next row included); inline, the FP64 steps
+// run 2-5% faster with the same results bit for bit.
+__device__ __forceinline__ double entry_flux(bool has_flux, const double *Mt,
                                              const double *lnM, int qt,
                                              double c, double Sm) {
   if (!has_flux) return 0.0;
@@ -139,22 +142,28 @@ __device__ __forceinline__ T pair_scale(const T *sg, int qa, int qb, bool ta,
   return s;
 }
 
-// One batch of rows [r, r + NB) of a lane's stream (rows at or past
-// r1 read as padding).  na, nb: the numbers of the entry's two bins (zero
-// exactly for inactive bins); on[u]: entry u is a pair of two active bins;
-// its operands are loaded only then (and the Courant number only if
-// with_c).
-template <int NB, typename Real, typename Real2, typename RealC>
-__device__ __forceinline__ void batch_fetch(
-    const uint2 *__restrict__ idx, const Real2 *__restrict__ ke,
-    const Real2 *__restrict__ xe, const RealC *__restrict__ ce, bool with_c,
-    int r, int r1, int lane, const Real *num, uint2 (&id)[NB],
-    bool (&on)[NB], Real (&na)[NB], Real (&nb)[NB], Real2 (&kb)[NB],
-    Real2 (&xb)[NB], RealC (&cb)[NB]) {
+// The entry words of one batch of rows [r, r + NB) of a lane's stream
+// (rows at or past r1 read as padding).
+template <int NB>
+__device__ __forceinline__ void batch_ids(const uint2 *__restrict__ idx,
+                                          int r, int r1, int lane,
+                                          uint2 (&id)[NB]) {
 #pragma unroll
   for (int u = 0; u < NB; ++u)
     id[u] = r + u < r1 ? idx[(size_t)(r + u) * kWave + lane]
                        : make_uint2(0u, 0u);
+}
+
+// The rest of a batch whose entry words id are loaded: na, nb, the numbers
+// of the entry's two bins (zero exactly for inactive bins); on[u]: entry u
+// is a pair of two active bins; its operands are loaded only then (and the
+// Courant number only if with_c).
+template <int NB, typename Real, typename Real2, typename RealC>
+__device__ __forceinline__ void batch_fetch(
+    const Real2 *__restrict__ ke, const Real2 *__restrict__ xe,
+    const RealC *__restrict__ ce, bool with_c, int r, int lane,
+    const Real *num, const uint2 (&id)[NB], bool (&on)[NB], Real (&na)[NB],
+    Real (&nb)[NB], Real2 (&kb)[NB], Real2 (&xb)[NB], RealC (&cb)[NB]) {
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int qa = (int)(id[u].x & 0xffffu), qb = (int)(id[u].x >> 16);
@@ -200,8 +209,10 @@ struct PassLds {
 
 // One step of one point by one wave (S1-S6).  Returns 1 if the limiter ran;
 // in FP32C mode it returns 2 and leaves the point untouched when the
-// limiter is needed (the caller takes that step in FP64 mode).
-template <bool F32>
+// limiter is needed (the caller takes that step in FP64 mode).  PF: load
+// the next batch's entry words while the current batch's operands are in
+// flight (it costs registers: the builds with room for them use it).
+template <bool F32, bool PF>
 __device__ unsigned point_step(const DevModel &m, const short *own_in,
                                double *st, int qs, double w, int br,
                                double dt, unsigned char *lds,
@@ -352,14 +363,23 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
           }
           first_flush = false;
         };
+        uint2 idn[NB];
+        if constexpr (PF) batch_ids<NB>(m.we_idx, r0, r1, lane, idn);
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
           Real na[NB], nb[NB];
           Real2 kb[NB], xb[NB];
           RealC cb[NB];
-          batch_fetch<NB>(m.we_idx, ke, xe, ce, true, r, r1, lane, nv, id,
-                          on, na, nb, kb, xb, cb);
+          if constexpr (PF) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) id[u] = idn[u];
+          } else {
+            batch_ids<NB>(m.we_idx, r, r1, lane, id);
+          }
+          batch_fetch<NB>(ke, xe, ce, true, r, lane, nv, id, on, na, nb, kb,
+                          xb, cb);
+          if constexpr (PF) batch_ids<NB>(m.we_idx, r + NB, r1, lane, idn);
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
             const unsigned fl = id[u].y >> 16;
@@ -469,14 +489,23 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
             P.merge(P.loss, cur, lo);
           first_flush = false;
         };
+        uint2 idn[NB];
+        if constexpr (PF) batch_ids<NB>(m.we_idx, r0, r1, lane, idn);
         for (int r = r0; r < r1; r += NB) {
           uint2 id[NB];
           bool on[NB];
           Real na[NB], nb[NB];
           Real2 kb[NB], xb[NB];
           RealC cb[NB];
-          batch_fetch<NB>(m.we_idx, ke, xe, ce, pass == 1, r, r1, lane, nv,
-                          id, on, na, nb, kb, xb, cb);
+          if constexpr (PF) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) id[u] = idn[u];
+          } else {
+            batch_ids<NB>(m.we_idx, r, r1, lane, id);
+          }
+          batch_fetch<NB>(ke, xe, ce, pass == 1, r, lane, nv, id, on, na, nb,
+                          kb, xb, cb);
+          if constexpr (PF) batch_ids<NB>(m.we_idx, r + NB, r1, lane, idn);
 #pragma unroll
           for (int u = 0; u < NB; ++u) {
             const unsigned fl = id[u].y >> 16;
@@ -593,7 +622,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
 // The steps of one slot: a launch's steps (FP32C: until a step needs the
 // limiter or drains a bin, then the slot is marked pending with the steps
 // of the call left), or the pending steps in FP64 mode.
-template <bool F32>
+template <bool F32, bool PF>
 __device__ __forceinline__ void slot_steps(const WaveArgs &a,
                                            const WaveGrid &G,
                                            const short *own, int slot,
@@ -618,7 +647,7 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
   const int n = a.pending_only ? pend : a.nsteps;
   for (int step = 0; step < n; ++step) {
     const unsigned r =
-        point_step<F32>(m, own, st, qs, w, br, a.dt, lds, npairs);
+        point_step<F32, PF>(m, own, st, qs, w, br, a.dt, lds, npairs);
     if (F32 && r == 2u) {
       if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
       break;
@@ -646,9 +675,14 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
 // some registers and is still about 20% faster than at 238 VGPRs and 2
 // waves (the entries' memory latency needs the waves).  Where the LDS of a
 // point already holds a CU below 3 waves per SIMD, the spills buy nothing,
-// and the FP64 build at 2 waves (no spills) runs instead; where it holds a
-// CU to 12 waves or fewer (no SIMD can get a fourth), FP32C mode runs at
-// 3 waves (138 VGPRs; 0.9% faster at 2 species x 132 bins).
+// and the FP64 build at 2 waves runs instead, with the entry words of the
+// next batch loaded ahead (a few registers spilled outside the pair loops;
+// 8% faster at 2 species x 132 bins, while at 3 waves the same prefetch
+// spills into them and four species ran 7% slower); where it holds a CU to
+// 12 waves or fewer (no SIMD can get a fourth), FP32C mode runs at 3 waves
+// (0.9% faster at 2 species x 132 bins than at 4), where its registers
+// leave room for the prefetch as well (145 VGPRs; 6% faster at 132 bins,
+// 11% at 264).
 template <bool F32, int W>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(W))) wave_step(WaveArgs a) {
@@ -684,7 +718,8 @@ __global__ void __launch_bounds__(kWave)
         own[o] = G.m.own[threadIdx.x * kMaxOwn + o];
       gown = g;
     }
-    slot_steps<F32>(a, G, own, slot, pv, lds, npairs, nlim, nfp64);
+    slot_steps<F32, F32 ? W == 3 : W == 2>(a, G, own, slot, pv, lds, npairs,
+                                           nlim, nfp64);
   }
   npairs = wave_sum_u64(npairs);
   if (threadIdx.x == 0) {
