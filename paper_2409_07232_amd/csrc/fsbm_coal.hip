@@ -221,6 +221,7 @@ void write_tune_cache(fsbm_coal_t h) {
 // gain and loss streams (see DevModel).
 struct WaveTables {
   std::vector<short> own;
+  int max_own = 0;  // bins a lane owns at most
   int rows_g = 0, rows_l = 0;
   std::vector<int> blk;  // [npairs][4]: gain rows offset, count; loss same
   std::vector<int> fixb; // [npairs][4]: gain fix-up offset, count; loss same
@@ -292,6 +293,7 @@ int build_wave_tables(fsbm_coal_t h, const std::vector<double> &Kd,
     wt.own[(size_t)best * kMaxOwn + cnt[best]++] = (short)q;
     load[best] += wgt[q];
   }
+  wt.max_own = *std::max_element(cnt.begin(), cnt.end());
   // Streams: per species pair (a <= b) and side, the entries of every bin
   // in bin order, cut into kWave contiguous segments of equal length (one
   // per lane, entry e of lane l at row e): every lane has work in every row
@@ -616,6 +618,7 @@ int build_model(fsbm_coal_t h, const double *tables, const double *plev) {
   m.ctfT = (const float *)at(13);
   m.xf = (const float *)at(14);
   m.own = (const short *)at(15);
+  m.wown = wt.max_own;
   m.wrows_g = wt.rows_g;
   m.wrows_l = wt.rows_l;
   m.we_idx = (const uint2 *)at(16);

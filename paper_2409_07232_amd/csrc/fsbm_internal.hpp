@@ -22,6 +22,7 @@ constexpr int kMaxBuckets = 64;
 constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
 constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
+constexpr int kOwnSmall = 4;       // its build for grids of few bins per lane
 constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
 // one-point-per-lane kernels for several species: species and S*B limits
 constexpr int kMultiMaxSpecies = 4;
@@ -79,6 +80,7 @@ struct DevModel {
   // blocks (wrows_l).  A bin whose entries span several lanes is shared
   // (kWShared) and is summed by a fix-up after its block (wfix).
   const short *own;
+  int wown;               // bins a lane owns at most (<= kMaxOwn)
   int wrows_g, wrows_l;
   const int *wblk;        // [npairs][4]: gain block row, rows; loss same
   const int *wfixb;       // [npairs][4]: gain fix-up offset, count; loss

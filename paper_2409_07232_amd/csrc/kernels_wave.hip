@@ -8,7 +8,10 @@
 //    the compacted points of every grid of the launch (persistent grid);
 //  * the point's bins are spread over the lanes by a load-balanced schedule
 //    built at create time; each lane owns up to kMaxOwn bins and keeps their
-//    accumulators in registers;
+//    accumulators in registers (a build for at most kOwnSmall bins per
+//    lane runs where the schedule fits it: four species at 33 bins and two
+//    at 66 hold 68 fewer spilled registers at 3 waves per SIMD, FP64 steps
+//    5-6% faster);
 //  * the point's masses, numbers and log-masses sit in LDS for all lanes;
 //  * each lane walks two precomputed streams of pair entries, interleaved by
 //    lane so that entry r of all 64 lanes is one coalesced load and the
@@ -212,16 +215,17 @@ struct PassLds {
 // limiter is needed (the caller takes that step in FP64 mode).  PF: load
 // the next batch's entry words while the current batch's operands are in
 // flight (it costs registers: the builds with room for them use it).
-template <bool F32, bool PF>
+// OWN: bins a lane owns at most (the grid's schedule fits it).
+template <bool F32, bool PF, int OWN>
 __device__ unsigned point_step(const DevModel &m, const short *own_in,
                                double *st, int qs, double w, int br,
                                double dt, unsigned char *lds,
                                unsigned long long &npairs) {
   // owned bins, opaque per step: keeps the compiler from holding per-bin
   // addresses in registers across steps
-  int own[kMaxOwn];
+  int own[OWN];
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
+  for (int o = 0; o < OWN; ++o) {
     own[o] = own_in[o];
     asm volatile("" : "+v"(own[o]));
   }
@@ -252,9 +256,9 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   // S1/S2: owned bins, FP64 total, activity.  The numbers and bin masses
   // of all owned bins are fetched before any is used; the bin k of
   // q = species B + k comes from one multiply (bmagic).
-  double no[kMaxOwn], xo[kMaxOwn];
+  double no[OWN], xo[OWN];
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
+  for (int o = 0; o < OWN; ++o) {
     const int q = own[o];
     const unsigned qq = q < 0 ? 0u : (unsigned)q;
     const unsigned k = qq - __umulhi(qq, m.bmagic) * (unsigned)B;
@@ -263,14 +267,14 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
   }
   double part = 0.0;
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o)
+  for (int o = 0; o < OWN; ++o)
     if (own[o] >= 0) part += no[o] * xo[o];
   const double Mtot = wave_sum_f64(part);
   const double thr = m.theta * Mtot;
   const double inv = Mtot > 0.0 ? 1.0 / Mtot : 0.0;
   uint64_t pres = 0;  // species with an active bin owned by this lane
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
+  for (int o = 0; o < OWN; ++o) {
     const int q = own[o];
     if (q < 0) continue;
     const double Mq = no[o] * xo[o];
@@ -575,7 +579,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     // error of ~1e-7 D / (M - D) into it, step after step.
     bool over = false;
 #pragma unroll
-    for (int o = 0; o < kMaxOwn; ++o) {
+    for (int o = 0; o < OWN; ++o) {
       const int q = own[o];
       if (q < 0) continue;
       const double Mq = (double)mass[q];
@@ -592,7 +596,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
     }
     // the second pass sums start from zero again
 #pragma unroll
-    for (int o = 0; o < kMaxOwn; ++o) {
+    for (int o = 0; o < OWN; ++o) {
       const int q = own[o];
       if (q < 0) continue;
       P.gain[q] = P.fout[q] = P.loss[q] = 0.0;
@@ -602,7 +606,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
 
   // S6: FP64 update of the owned bins
 #pragma unroll
-  for (int o = 0; o < kMaxOwn; ++o) {
+  for (int o = 0; o < OWN; ++o) {
     const int q = own[o];
     if (q < 0) continue;
     const int k = q - (int)__umulhi((unsigned)q, m.bmagic) * B;
@@ -622,7 +626,7 @@ __device__ unsigned point_step(const DevModel &m, const short *own_in,
 // The steps of one slot: a launch's steps (FP32C: until a step needs the
 // limiter or drains a bin, then the slot is marked pending with the steps
 // of the call left), or the pending steps in FP64 mode.
-template <bool F32, bool PF>
+template <bool F32, bool PF, int OWN>
 __device__ __forceinline__ void slot_steps(const WaveArgs &a,
                                            const WaveGrid &G,
                                            const short *own, int slot,
@@ -647,7 +651,7 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
   const int n = a.pending_only ? pend : a.nsteps;
   for (int step = 0; step < n; ++step) {
     const unsigned r =
-        point_step<F32, PF>(m, own, st, qs, w, br, a.dt, lds, npairs);
+        point_step<F32, PF, OWN>(m, own, st, qs, w, br, a.dt, lds, npairs);
     if (F32 && r == 2u) {
       if (threadIdx.x == 0) G.pending[slot] = a.steps_left - step;
       break;
@@ -683,7 +687,13 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
 // (0.9% faster at 2 species x 132 bins than at 4), where its registers
 // leave room for the prefetch as well (145 VGPRs; 6% faster at 132 bins,
 // 11% at 264).
-template <bool F32, int W>
+// Builds that load the next batch's entry words ahead: those whose
+// registers hold them without spilling into the pair loops.
+constexpr bool wave_prefetch(bool f32, int w, int own) {
+  return f32 ? (w == 3 || own <= kOwnSmall) : w == 2;
+}
+
+template <bool F32, int W, int OWN>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(W))) wave_step(WaveArgs a) {
   extern __shared__ unsigned char lds[];
@@ -694,7 +704,7 @@ __global__ void __launch_bounds__(kWave)
       (unsigned long long)a.launch_idx *
       (unsigned long long)(total + (long long)gridDim.x);
   int gown = -1;
-  short own[kMaxOwn];
+  short own[OWN];
   for (;;) {
     unsigned long long t = 0;
     if (threadIdx.x == 0) t = atomicAdd(&a.counters[3], 1ull);
@@ -714,12 +724,12 @@ __global__ void __launch_bounds__(kWave)
     if (a.pending_only ? pv <= 0 : pv != 0) continue;
     if (g != gown) {
 #pragma unroll
-      for (int o = 0; o < kMaxOwn; ++o)
+      for (int o = 0; o < OWN; ++o)
         own[o] = G.m.own[threadIdx.x * kMaxOwn + o];
       gown = g;
     }
-    slot_steps<F32, F32 ? W == 3 : W == 2>(a, G, own, slot, pv, lds, npairs,
-                                           nlim, nfp64);
+    slot_steps<F32, wave_prefetch(F32, W, OWN), OWN>(a, G, own, slot, pv, lds,
+                                                     npairs, nlim, nfp64);
   }
   npairs = wave_sum_u64(npairs);
   if (threadIdx.x == 0) {
@@ -731,13 +741,28 @@ __global__ void __launch_bounds__(kWave)
   }
 }
 
+// The build for the launch's occupancy target, by the bins a lane owns.
+template <bool F32, int W>
+void launch_own(const WaveArgs &a, int own, int blocks, size_t lds,
+                hipStream_t st) {
+  if (own <= kOwnSmall)
+    hipLaunchKernelGGL((wave_step<F32, W, kOwnSmall>), dim3(blocks),
+                       dim3(kWave), lds, st, a);
+  else
+    hipLaunchKernelGGL((wave_step<F32, W, kMaxOwn>), dim3(blocks),
+                       dim3(kWave), lds, st, a);
+}
+
 }  // namespace
 
 hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
                             hipStream_t st) {
-  int sb = 0;
-  for (int g = 0; g < a.ngrids; ++g)
+  int sb = 0, own = 0;
+  for (int g = 0; g < a.ngrids; ++g) {
     sb = a.g[g].m.S * a.g[g].m.B > sb ? a.g[g].m.S * a.g[g].m.B : sb;
+    own = a.g[g].m.wown > own ? a.g[g].m.wown : own;
+  }
+  if (own < 1 || own > kMaxOwn) return hipErrorInvalidValue;
   // LDS per wave (see point_step): 3 Real per bin, padded to 8 bytes, 4
   // FP64 sums and a limiter factor (FP64) or an exponent (FP32C) per bin,
   // then the partial sums of shared bins
@@ -749,17 +774,13 @@ hipError_t launch_wave_step(const WaveArgs &a, int precision, int blocks,
   // fourth wave on some SIMD needs room for 13
   constexpr size_t kLdsPerCu = 160 * 1024;
   if (f64 && lds * 12 <= kLdsPerCu)
-    hipLaunchKernelGGL((wave_step<false, 3>), dim3(blocks), dim3(kWave), lds,
-                       st, a);
+    launch_own<false, 3>(a, own, blocks, lds, st);
   else if (f64)
-    hipLaunchKernelGGL((wave_step<false, 2>), dim3(blocks), dim3(kWave), lds,
-                       st, a);
+    launch_own<false, 2>(a, own, blocks, lds, st);
   else if (lds * 13 <= kLdsPerCu)
-    hipLaunchKernelGGL((wave_step<true, 4>), dim3(blocks), dim3(kWave), lds,
-                       st, a);
+    launch_own<true, 4>(a, own, blocks, lds, st);
   else
-    hipLaunchKernelGGL((wave_step<true, 3>), dim3(blocks), dim3(kWave), lds,
-                       st, a);
+    launch_own<true, 3>(a, own, blocks, lds, st);
   return hipGetLastError();
 }
 
