@@ -22,7 +22,8 @@ constexpr int kMaxBuckets = 64;
 constexpr int kLaneMaxBins = 40;   // one-point-per-lane kernel: S*B limit
 constexpr int kSlotAlign = 256;    // slot capacity granularity (>= block)
 constexpr int kMaxOwn = 12;        // one-point-per-wave kernel: bins per lane
-constexpr int kOwnSmall = 4;       // its build for grids of few bins per lane
+constexpr int kOwnSmall = 4;       // its builds for grids of fewer bins
+constexpr int kOwnMid = 8;         //   per lane
 constexpr int kMaxGrids = 4;       // grids in one multi-grid launch
 // one-point-per-lane kernels for several species: species and S*B limits
 constexpr int kMultiMaxSpecies = 4;

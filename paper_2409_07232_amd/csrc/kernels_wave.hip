@@ -8,10 +8,11 @@
 //    the compacted points of every grid of the launch (persistent grid);
 //  * the point's bins are spread over the lanes by a load-balanced schedule
 //    built at create time; each lane owns up to kMaxOwn bins and keeps their
-//    accumulators in registers (a build for at most kOwnSmall bins per
-//    lane runs where the schedule fits it: four species at 33 bins and two
-//    at 66 hold 68 fewer spilled registers at 3 waves per SIMD, FP64 steps
-//    5-6% faster);
+//    accumulators in registers (builds for at most kOwnSmall or kOwnMid
+//    bins per lane run where the schedule fits them: four species at 33
+//    bins and two at 66 hold 68 fewer spilled registers at 3 waves per
+//    SIMD, FP64 steps 5-6% faster; two species at 132 bins and the mixed
+//    batch none at 2 waves, 2-4.5% faster);
 //  * the point's masses, numbers and log-masses sit in LDS for all lanes;
 //  * each lane walks two precomputed streams of pair entries, interleaved by
 //    lane so that entry r of all 64 lanes is one coalesced load and the
@@ -747,6 +748,9 @@ void launch_own(const WaveArgs &a, int own, int blocks, size_t lds,
                 hipStream_t st) {
   if (own <= kOwnSmall)
     hipLaunchKernelGGL((wave_step<F32, W, kOwnSmall>), dim3(blocks),
+                       dim3(kWave), lds, st, a);
+  else if (own <= kOwnMid)
+    hipLaunchKernelGGL((wave_step<F32, W, kOwnMid>), dim3(blocks),
                        dim3(kWave), lds, st, a);
   else
     hipLaunchKernelGGL((wave_step<F32, W, kMaxOwn>), dim3(blocks),
