@@ -44,9 +44,9 @@ if ROOT not in sys.path:
 # Algorithmic work per evaluated bin pair: 24 floating-point operations
 # (interpolated kernel 2, collided masses 5, merged mass 1, neighbour ratio
 # 2, slope 2, flux fraction 4, clamps 2, flux 1, net combine 2, per-bin
-# accumulation 4; the survey of the method's cost counts these), plus 2
-# divisions and 3 transcendentals (log, exp, expm1) that are not counted as
-# flops.  OPS_PER_PAIR_ALL counts each of those once as well.
+# accumulation 4: the operations of one pair's update as the method states
+# it), plus 2 divisions and 3 transcendentals (log, exp, expm1) that are not
+# counted as flops.  OPS_PER_PAIR_ALL counts each of those once as well.
 FLOPS_PER_PAIR = 24
 OPS_PER_PAIR_ALL = 29
 FP32C_TOL = 1e-5           # rel_bin bar of the FP32C path
