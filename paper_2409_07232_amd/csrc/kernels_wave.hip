@@ -665,6 +665,12 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
   }
 }
 
+// Builds that load the next batch's entry words ahead: those whose
+// registers hold them without spilling into the pair loops.
+constexpr bool wave_prefetch(bool f32, int w, int own) {
+  return f32 ? (w == 3 || own <= kOwnSmall) : w == 2;
+}
+
 // Persistent waves over the compacted slots of every grid, handed out one
 // at a time from a counter (counters[3], zero at the start of the call): a
 // point's cost varies with its species and spectrum, and the FP64 steps of
@@ -688,12 +694,6 @@ __device__ __forceinline__ void slot_steps(const WaveArgs &a,
 // (0.9% faster at 2 species x 132 bins than at 4), where its registers
 // leave room for the prefetch as well (145 VGPRs; 6% faster at 132 bins,
 // 11% at 264).
-// Builds that load the next batch's entry words ahead: those whose
-// registers hold them without spilling into the pair loops.
-constexpr bool wave_prefetch(bool f32, int w, int own) {
-  return f32 ? (w == 3 || own <= kOwnSmall) : w == 2;
-}
-
 template <bool F32, int W, int OWN>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(W))) wave_step(WaveArgs a) {
