@@ -75,6 +75,10 @@ MEASURED_TRAFFIC = {
         LANE_SOURCES,
         "f6d1ade88a1b6d690439e81f670bc3a8ae865d7d744d9f968b6162bb46b754b6",
         2.9020e9, _PROF_LANE),
+    ("lane_seq_f64<33>", "thunderstorm_patch_256x256x50_33bins_liquid"): (
+        ("kernels_seq.hip", "device_common.hpp", "fp64_math.hpp"),
+        "e3d3533ecc1db38a43a7235d0aca79d908879dc407321d5ca9978f3076c4b3d9",
+        2.671e8, _PROF_LANE),
     # the four launches (NS = 1..4) of a group of steps together
     ("lane_multi_f32c<33,NS=1..4>", "four_species_1048576pts_33bins"): (
         ("kernels_multi.hip", "device_common.hpp", "fp64_math.hpp"),
