@@ -85,6 +85,13 @@ MEASURED_TRAFFIC = {
         "7af86f1ccac6ca324a79a6f47cb61d7cbb72de42e50dcc87239980aae7c326fe",
         1.7022e10,
         "profiles/lane_multi_four_species_1048576x33.md"),
+    # the FP64 path's 10-step launches (scratch of spilled registers
+    # included)
+    ("wave_step<F64>", "four_species_1048576pts_33bins"): (
+        ("kernels_wave.hip", "device_common.hpp", "fp64_math.hpp"),
+        "236bf87b9101be5cc136069b4072f863b97c311810b25e69096d368f34ac0e4b",
+        3.898e10,
+        "profiles/lane_multi_four_species_1048576x33.md"),
     ("cond_steps<33>", "thunderstorm_patch_256x256x50_33bins_liquid_"
                        "prescribed_supersaturation"): (
         ("condense.hip", "device_common.hpp", "fp64_math.hpp"),
